@@ -1,0 +1,107 @@
+"""ctypes declarations of the C ABI in include/phi4pmc.h."""
+
+import ctypes
+import os
+
+PHI4_OK, PHI4_DONE = 0, 1
+PHI4_EINVAL, PHI4_EHIP, PHI4_ECHOL, PHI4_ENONFINITE = -1, -2, -3, -4
+PHI4_FP32, PHI4_BF16, PHI4_FP16 = 0, 1, 2
+PHI4_INIT, PHI4_PROPOSE, PHI4_ACCEPT, PHI4_RESAMPLE, PHI4_NS_PICK = 1, 2, 3, 4, 5
+PHI4_MAX_SITES = 256
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libphi4pmc.so")
+
+
+class Phi4Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(msg)
+        self.code = code
+
+
+class SmcConfig(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int32),
+        ("N", ctypes.c_int32),
+        ("m2", ctypes.c_double),
+        ("lambda_", ctypes.c_double),
+        ("ess_frac", ctypes.c_double),
+        ("n_steps", ctypes.c_int32),
+        ("acc_target", ctypes.c_double),
+        ("eps0", ctypes.c_double),
+        ("seed", ctypes.c_uint32),
+        ("run", ctypes.c_uint32),
+        ("precision", ctypes.c_int32),
+    ]
+
+
+class NsConfig(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int32),
+        ("n_live", ctypes.c_int32),
+        ("k_delete", ctypes.c_int32),
+        ("n_steps", ctypes.c_int32),
+        ("m2", ctypes.c_double),
+        ("lambda_", ctypes.c_double),
+        ("prior_var", ctypes.c_double),
+        ("term_frac", ctypes.c_double),
+        ("acc_target", ctypes.c_double),
+        ("eps0", ctypes.c_double),
+        ("seed", ctypes.c_uint32),
+        ("run", ctypes.c_uint32),
+        ("precision", ctypes.c_int32),
+    ]
+
+
+_V, _I32, _U32, _D, _F, _SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32,
+                                ctypes.c_double, ctypes.c_float, ctypes.c_size_t)
+_PD = ctypes.POINTER(ctypes.c_double)
+_PI = ctypes.POINTER(ctypes.c_int32)
+
+# name -> (restype, argtypes); every symbol of include/phi4pmc.h
+SIGNATURES = {
+    "smc_workspace_bytes": (_SZ, [ctypes.POINTER(SmcConfig)]),
+    "smc_init": (ctypes.c_int, [ctypes.POINTER(SmcConfig), _V, _V, _V, _SZ, _V,
+                                ctypes.POINTER(ctypes.c_void_p)]),
+    "smc_restart": (ctypes.c_int, [_V, _U32, _U32]),
+    "smc_reweight_resample": (ctypes.c_int, [_V, _PD]),
+    "smc_mutate": (ctypes.c_int, [_V, _PD]),
+    "smc_run": (ctypes.c_int, [_V, _I32, _PI]),
+    "ns_workspace_bytes": (_SZ, [ctypes.POINTER(NsConfig)]),
+    "ns_init": (ctypes.c_int, [ctypes.POINTER(NsConfig), _V, _V, _V, _SZ, _V,
+                               ctypes.POINTER(ctypes.c_void_p)]),
+    "ns_step": (ctypes.c_int, [_V, _PI]),
+    "logz": (ctypes.c_int, [_V, _PD, _PD]),
+    "phi4_observables": (ctypes.c_int, [_V, _PD]),
+    "phi4_set_timing": (ctypes.c_int, [_V, _I32]),
+    "phi4_kernel_time": (ctypes.c_int, [_V, _PD, _PI]),
+    "phi4_destroy": (ctypes.c_int, [_V]),
+    "phi4_last_error": (ctypes.c_char_p, []),
+    "phi4_normals": (ctypes.c_int, [_U32, _U32, _I32, _I32, _I32, _V, _I32, _I32, _V, _V]),
+    "phi4_action": (ctypes.c_int, [_V, _I32, _I32, _D, _D, _V, _V, _V]),
+    "phi4_resample_systematic": (ctypes.c_int, [_V, _I32, _U32, _V, _V, _SZ, _V]),
+    "phi4_reweight": (ctypes.c_int, [_V, _I32, _D, _D, _V, _PD, _V, _SZ, _V]),
+    "phi4_covariance": (ctypes.c_int, [_V, _V, _I32, _I32, _V, _V, _SZ, _V]),
+    "phi4_cholesky": (ctypes.c_int, [_V, _I32, _V, _PD, _V, _SZ, _V]),
+    "phi4_step_workspace_bytes": (_SZ, [_I32, _I32]),
+    "phi4_mutate": (ctypes.c_int, [_V, _V, _V, _I32, _I32, _D, _D, _V, _I32, _D, _D, _D, _U32,
+                                   _U32, _I32, _I32, _I32, _F, _I32, _V, _V, _V, _V, _V, _V]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(library_path):
+            raise ImportError(f"{library_path} is missing: run __graft_entry__.build() or "
+                              "python paper_2511_15196_amd/build.py")
+        handle = ctypes.CDLL(library_path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib

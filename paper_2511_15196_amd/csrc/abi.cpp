@@ -1,0 +1,883 @@
+// C ABI of libphi4pmc: argument checks, workspace carving, handles and the
+// native level loop.  Every compute step runs in the HIP kernels of this
+// library; this file only validates, orders and launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "common.hpp"
+
+using namespace phi4;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_check(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(PHI4_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  return PHI4_OK;
+}
+
+#define HIP_TRY(call)                                                                     \
+  do {                                                                                    \
+    const hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess) return fail(PHI4_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+
+// Sequential carving of a caller-provided workspace.
+struct Carver {
+  uintptr_t base;
+  size_t off = 0;
+  explicit Carver(void* p) : base(reinterpret_cast<uintptr_t>(p)) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    T* p = reinterpret_cast<T*>(base + off);
+    off += count * sizeof(T);
+    return p;
+  }
+  size_t bytes() const { return (off + kAlign - 1) / kAlign * kAlign; }
+};
+
+double default_eps0(int d, double eps0) { return eps0 > 0 ? eps0 : 2.38 / std::sqrt((double)d); }
+
+// ------------------------------------------------------------------ SMC
+
+struct SmcBufs {
+  SmcState* st;
+  float* alt_phi;
+  float* alt_S;
+  float* absM;
+  float* obs_S;
+  float* obs_absM;
+  double* obs_mean;
+  int32_t* anc;
+  unsigned long long* cdf;
+  int32_t* marks;
+  double* w;
+  float* part;
+  double* sigma;
+  double* A;
+  float* Bt;
+};
+
+size_t smc_carve(const phi4_smc_config& c, void* ws, SmcBufs* b) {
+  const int d = c.L * c.L, n = c.N;
+  const CovPlan plan = cov_plan(n, d);
+  Carver cv(ws);
+  SmcBufs t;
+  t.st = cv.take<SmcState>(1);
+  t.alt_phi = cv.take<float>((size_t)n * d);
+  t.alt_S = cv.take<float>(n);
+  t.absM = cv.take<float>(n);
+  t.obs_S = cv.take<float>(n);
+  t.obs_absM = cv.take<float>(n);
+  t.obs_mean = cv.take<double>(1);
+  t.anc = cv.take<int32_t>(n);
+  t.cdf = cv.take<unsigned long long>(n);
+  t.marks = cv.take<int32_t>(n);
+  t.w = cv.take<double>(n);
+  t.part = cv.take<float>(cov_partial_floats(plan));
+  t.sigma = cv.take<double>((size_t)d * d);
+  t.A = cv.take<double>((size_t)d * d);
+  t.Bt = cv.take<float>((size_t)d * d);
+  if (b) *b = t;
+  return cv.bytes();
+}
+
+bool smc_valid(const phi4_smc_config* c, std::string* why) {
+  if (!c) return *why = "config is NULL", false;
+  const long long d = (long long)c->L * c->L;
+  if (c->L < 1 || d > PHI4_MAX_SITES) return *why = "need 1 <= L and L*L <= 256", false;
+  if (c->N < 2 || c->N > (1 << 24)) return *why = "need 2 <= N <= 2^24", false;
+  if (!(c->ess_frac > 0.0 && c->ess_frac <= 1.0)) return *why = "ess_frac must be in (0, 1]", false;
+  if (c->n_steps < 0) return *why = "n_steps must be >= 0", false;
+  if (!std::isfinite(c->m2) || !std::isfinite(c->lambda)) return *why = "couplings must be finite", false;
+  if (!mutate_supported((int)d, c->precision)) return *why = "unsupported precision", false;
+  return true;
+}
+
+struct Handle {
+  int kind;  // 0 SMC, 1 NS
+  hipStream_t stream;
+  float* phi;
+  float* S;
+  int L, d, n;
+  float m2, lam;
+  uint32_t seed, run;
+  int precision;
+  int n_steps;
+  // SMC
+  phi4_smc_config smc;
+  SmcBufs sb;
+  int cur;  // 0: particles in phi/S, 1: in the workspace copy
+  CovPlan plan;
+  // NS
+  phi4_ns_config ns;
+  NsState* nst;
+  float* absM;
+  int32_t* dead;
+  int32_t* surv;
+  double* scratch;
+  float* part;
+  double* sigma;
+  double* A;
+  float* Bt;
+  CovPlan nplan;
+  // host mirrors
+  void* pinned;  // two state copies
+  hipEvent_t ev[2];
+  // kernel timing
+  bool timing;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;  // event pool
+  size_t tused;                                        // pairs recorded
+};
+
+// Brackets one mutation launch with a pair of timing events.
+struct TimedLaunch {
+  Handle* h;
+  hipEvent_t stop = nullptr;
+  explicit TimedLaunch(Handle* hh) : h(hh) {
+    if (!h->timing) return;
+    if (h->tused == h->tev.size()) {
+      std::pair<hipEvent_t, hipEvent_t> p{nullptr, nullptr};
+      if (hipEventCreate(&p.first) != hipSuccess || hipEventCreate(&p.second) != hipSuccess) {
+        h->timing = false;
+        return;
+      }
+      h->tev.push_back(p);
+    }
+    (void)hipEventRecord(h->tev[h->tused].first, h->stream);
+    stop = h->tev[h->tused].second;
+  }
+  ~TimedLaunch() {
+    if (!stop) return;
+    (void)hipEventRecord(stop, h->stream);
+    ++h->tused;
+  }
+};
+
+int copy_state(Handle* h, void* host, size_t bytes, const void* dev) {
+  HIP_TRY(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return PHI4_OK;
+}
+
+int state_error(int err) {
+  if (err == PHI4_ECHOL) return fail(PHI4_ECHOL, "covariance not positive definite after jitter");
+  if (err == PHI4_ENONFINITE) return fail(PHI4_ENONFINITE, "non-finite actions or weights");
+  return fail(err, "device error");
+}
+
+int enqueue_reweight(Handle* h) {
+  SmcBufs& b = h->sb;
+  float* curS = h->cur ? b.alt_S : h->S;
+  float* curP = h->cur ? b.alt_phi : h->phi;
+  float* othS = h->cur ? h->S : b.alt_S;
+  float* othP = h->cur ? h->phi : b.alt_phi;
+  ReweightArgs ra = {};
+  ra.S = curS;
+  ra.n = h->n;
+  ra.st = b.st;
+  ra.w = b.w;
+  ra.seed = h->seed;
+  ra.run = h->run;
+  ra.do_resample = 1;
+  ra.cdf = b.cdf;
+  ra.marks = b.marks;
+  ra.anc = b.anc;
+  launch_reweight(ra, h->stream);
+  launch_gather(curP, curS, b.anc, h->n, h->d, othP, othS, nullptr, h->stream);
+  h->cur ^= 1;
+  float* newP = h->cur ? b.alt_phi : h->phi;
+  launch_cov_partials(newP, nullptr, h->plan, b.part, &b.st->done, h->stream);
+  FactorArgs fa = {};
+  fa.part = b.part;
+  fa.plan = h->plan;
+  fa.sigma_out = b.sigma;
+  fa.A = b.A;
+  fa.Bt = b.Bt;
+  fa.ldb = h->d;
+  fa.eps_ptr = &b.st->eps;
+  fa.tau_out = &b.st->tau;
+  fa.err_out = &b.st->err;
+  fa.done = &b.st->done;
+  launch_factor(fa, h->stream);
+  return hip_check("smc_reweight_resample");
+}
+
+int enqueue_mutate(Handle* h) {
+  SmcBufs& b = h->sb;
+  MutateArgs m = {};
+  m.src = h->cur ? b.alt_phi : h->phi;
+  m.dst = h->phi;
+  m.rows = nullptr;
+  m.n = h->n;
+  m.L = h->L;
+  m.d = h->d;
+  m.m2 = h->m2;
+  m.lam = h->lam;
+  m.Bt = b.Bt;
+  m.ldb = h->d;
+  m.kind = 0;
+  m.beta_ptr = &b.st->beta;
+  m.seed = h->seed;
+  m.run = h->run;
+  m.level_ptr = &b.st->level;
+  m.step0 = 0;
+  m.n_steps = h->n_steps;
+  m.zsign = 1.0f;
+  m.done_ptr = &b.st->done;
+  m.S = h->S;
+  m.absM = b.absM;
+  m.acc_count = &b.st->acc;
+  m.prop_count = &b.st->prop;
+  int rc;
+  {
+    TimedLaunch tl(h);
+    rc = launch_mutate(m, h->precision, h->stream);
+  }
+  if (rc) return fail(rc, "smc_mutate: unsupported shape");
+  h->cur = 0;
+  return hip_check("smc_mutate");
+}
+
+Handle* as_handle(void* p, int kind) {
+  Handle* h = static_cast<Handle*>(p);
+  if (!h || h->kind != kind) return nullptr;
+  return h;
+}
+
+int alloc_pinned(Handle* h, size_t bytes) {
+  HIP_TRY(hipHostMalloc(&h->pinned, 2 * bytes, hipHostMallocDefault));
+  HIP_TRY(hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming));
+  return PHI4_OK;
+}
+
+// ------------------------------------------------------------------ NS
+
+size_t ns_carve(const phi4_ns_config& c, void* ws, Handle* h) {
+  const int d = c.L * c.L, n = c.n_live, k = c.k_delete;
+  const CovPlan plan = cov_plan(n - k, d);
+  Carver cv(ws);
+  NsState* st = cv.take<NsState>(1);
+  float* absM = cv.take<float>(n);
+  int32_t* dead = cv.take<int32_t>(k);
+  int32_t* surv = cv.take<int32_t>(n - k);
+  double* scratch = cv.take<double>(2 * (size_t)k);
+  float* part = cv.take<float>(cov_partial_floats(plan));
+  double* sigma = cv.take<double>((size_t)d * d);
+  double* A = cv.take<double>((size_t)d * d);
+  float* Bt = cv.take<float>((size_t)d * d);
+  if (h) {
+    h->nst = st;
+    h->absM = absM;
+    h->dead = dead;
+    h->surv = surv;
+    h->scratch = scratch;
+    h->part = part;
+    h->sigma = sigma;
+    h->A = A;
+    h->Bt = Bt;
+    h->nplan = plan;
+  }
+  return cv.bytes();
+}
+
+bool ns_valid(const phi4_ns_config* c, std::string* why) {
+  if (!c) return *why = "config is NULL", false;
+  const long long d = (long long)c->L * c->L;
+  if (c->L < 1 || d > PHI4_MAX_SITES) return *why = "need 1 <= L and L*L <= 256", false;
+  if (c->n_live < 3 || c->n_live > 8192) return *why = "need 3 <= n_live <= 8192", false;
+  if (c->k_delete < 1 || c->k_delete > c->n_live - 2) return *why = "need 1 <= k_delete <= n_live - 2", false;
+  if (c->n_steps < 0) return *why = "n_steps must be >= 0", false;
+  if (!(c->prior_var > 0.0) || !std::isfinite(c->prior_var)) return *why = "prior_var must be > 0", false;
+  if (!(c->term_frac > 0.0 && c->term_frac < 1.0)) return *why = "term_frac must be in (0, 1)", false;
+  if (!std::isfinite(c->m2) || !std::isfinite(c->lambda)) return *why = "couplings must be finite", false;
+  if (!mutate_supported((int)d, c->precision)) return *why = "unsupported precision", false;
+  return true;
+}
+
+NsArgs ns_args(Handle* h) {
+  NsArgs a = {};
+  a.phi = h->phi;
+  a.S = h->S;
+  a.absM = h->absM;
+  a.n = h->n;
+  a.k = h->ns.k_delete;
+  a.d = h->d;
+  a.st = h->nst;
+  a.seed = h->seed;
+  a.run = h->run;
+  a.dead_rows = h->dead;
+  a.surv_rows = h->surv;
+  a.scratch = h->scratch;
+  a.term_frac = h->ns.term_frac;
+  return a;
+}
+
+// step-level workspace
+struct StepBufs {
+  unsigned long long* cdf;
+  int32_t* marks;
+  int32_t* status;
+  double* out;
+  float* part;
+  double* sigma;
+  double* A;
+  double* tau;
+};
+
+size_t step_carve(int n, int d, void* ws, StepBufs* b) {
+  Carver cv(ws);
+  StepBufs t;
+  t.cdf = cv.take<unsigned long long>(n > 0 ? n : 1);
+  t.marks = cv.take<int32_t>(n > 0 ? n : 1);
+  t.status = cv.take<int32_t>(4);
+  t.out = cv.take<double>(8);
+  const int dd = d > 0 ? d : 1;
+  t.part = cv.take<float>(cov_partial_floats(cov_plan(n > 1 ? n : 2, dd)));
+  t.sigma = cv.take<double>((size_t)dd * dd);
+  t.A = cv.take<double>((size_t)dd * dd);
+  t.tau = cv.take<double>(1);
+  if (b) *b = t;
+  return cv.bytes();
+}
+
+bool ws_ok(void* ws, size_t have, size_t need, std::string* why) {
+  if (!ws) return *why = "workspace is NULL", false;
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return *why = "workspace must be 256-byte aligned", false;
+  if (have < need) return *why = "workspace too small: need " + std::to_string(need) + " bytes", false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* phi4_last_error(void) { return g_err.c_str(); }
+
+size_t smc_workspace_bytes(const phi4_smc_config* cfg) {
+  std::string why;
+  if (!smc_valid(cfg, &why)) return 0;
+  return smc_carve(*cfg, nullptr, nullptr);
+}
+
+int smc_init(const phi4_smc_config* cfg, float* phi, float* S, void* workspace,
+             size_t workspace_bytes, void* stream, void** handle) {
+  std::string why;
+  if (!handle) return fail(PHI4_EINVAL, "handle is NULL");
+  *handle = nullptr;
+  if (!smc_valid(cfg, &why)) return fail(PHI4_EINVAL, "smc_init: " + why);
+  if (!phi || !S) return fail(PHI4_EINVAL, "smc_init: phi / S is NULL");
+  if (!ws_ok(workspace, workspace_bytes, smc_carve(*cfg, nullptr, nullptr), &why))
+    return fail(PHI4_EINVAL, "smc_init: " + why);
+  Handle* h = new (std::nothrow) Handle();
+  if (!h) return fail(PHI4_EINVAL, "smc_init: out of host memory");
+  h->kind = 0;
+  h->stream = static_cast<hipStream_t>(stream);
+  h->phi = phi;
+  h->S = S;
+  h->L = cfg->L;
+  h->d = cfg->L * cfg->L;
+  h->n = cfg->N;
+  h->m2 = (float)cfg->m2;
+  h->lam = (float)cfg->lambda;
+  h->seed = cfg->seed;
+  h->run = cfg->run;
+  h->precision = cfg->precision;
+  h->n_steps = cfg->n_steps;
+  h->smc = *cfg;
+  h->cur = 0;
+  h->plan = cov_plan(h->n, h->d);
+  smc_carve(*cfg, workspace, &h->sb);
+  int rc = alloc_pinned(h, sizeof(SmcState));
+  if (rc) {
+    delete h;
+    return rc;
+  }
+  launch_smc_state_init(h->sb.st, default_eps0(h->d, cfg->eps0), cfg->acc_target, cfg->ess_frac,
+                        h->stream);
+  launch_init_fields(phi, S, h->sb.absM, h->n, h->L, h->m2, h->lam, 1.0f, h->seed, h->run,
+                     h->stream);
+  rc = hip_check("smc_init");
+  if (rc) {
+    phi4_destroy(h);
+    return rc;
+  }
+  *handle = h;
+  return PHI4_OK;
+}
+
+int smc_restart(void* handle, uint32_t seed, uint32_t run) {
+  Handle* h = as_handle(handle, 0);
+  if (!h) return fail(PHI4_EINVAL, "smc_restart: not an SMC handle");
+  h->seed = seed;
+  h->run = run;
+  h->smc.seed = seed;
+  h->smc.run = run;
+  h->cur = 0;
+  launch_smc_state_init(h->sb.st, default_eps0(h->d, h->smc.eps0), h->smc.acc_target,
+                        h->smc.ess_frac, h->stream);
+  launch_init_fields(h->phi, h->S, h->sb.absM, h->n, h->L, h->m2, h->lam, 1.0f, seed, run,
+                     h->stream);
+  return hip_check("smc_restart");
+}
+
+int smc_reweight_resample(void* handle, double* beta_host) {
+  Handle* h = as_handle(handle, 0);
+  if (!h) return fail(PHI4_EINVAL, "smc_reweight_resample: not an SMC handle");
+  int rc = enqueue_reweight(h);
+  if (rc) return rc;
+  if (!beta_host) return PHI4_OK;
+  SmcState* s = static_cast<SmcState*>(h->pinned);
+  rc = copy_state(h, s, sizeof(SmcState), h->sb.st);
+  if (rc) return rc;
+  if (s->err) return state_error(s->err);
+  *beta_host = s->beta;
+  return s->done ? PHI4_DONE : PHI4_OK;
+}
+
+int smc_mutate(void* handle, double* acc_host) {
+  Handle* h = as_handle(handle, 0);
+  if (!h) return fail(PHI4_EINVAL, "smc_mutate: not an SMC handle");
+  int rc = enqueue_mutate(h);
+  if (rc) return rc;
+  if (!acc_host) return PHI4_OK;
+  SmcState* s = static_cast<SmcState*>(h->pinned);
+  rc = copy_state(h, s, sizeof(SmcState), h->sb.st);
+  if (rc) return rc;
+  if (s->err) return state_error(s->err);
+  *acc_host = s->prop ? (double)s->acc / (double)s->prop : NAN;
+  return s->done ? PHI4_DONE : PHI4_OK;
+}
+
+int smc_run(void* handle, int32_t max_levels, int32_t* levels_host) {
+  Handle* h = as_handle(handle, 0);
+  if (!h) return fail(PHI4_EINVAL, "smc_run: not an SMC handle");
+  if (max_levels < 1) return fail(PHI4_EINVAL, "smc_run: max_levels must be >= 1");
+  SmcState* slots = static_cast<SmcState*>(h->pinned);
+  // Level t is enqueued before the state after level t-1 is inspected, so
+  // the device always has the next level queued; the one level enqueued
+  // after the final sweep finds beta = 1 and does nothing.
+  int rc = PHI4_OK;
+  bool finished = false;
+  for (int t = 0; t < max_levels && !finished; ++t) {
+    rc = enqueue_reweight(h);
+    if (!rc) rc = enqueue_mutate(h);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(&slots[t & 1], h->sb.st, sizeof(SmcState), hipMemcpyDeviceToHost,
+                           h->stream));
+    HIP_TRY(hipEventRecord(h->ev[t & 1], h->stream));
+    if (t >= 1) {
+      HIP_TRY(hipEventSynchronize(h->ev[(t - 1) & 1]));
+      const SmcState& s = slots[(t - 1) & 1];
+      if (s.err) return state_error(s.err);
+      if (s.beta >= 1.0) finished = true;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  // the level enqueued after the final sweep did no work: drop its timing
+  if (finished && h->timing && h->tused > 0) --h->tused;
+  SmcState s;
+  rc = copy_state(h, &slots[0], sizeof(SmcState), h->sb.st);
+  if (rc) return rc;
+  s = slots[0];
+  if (s.err) return state_error(s.err);
+  if (levels_host) *levels_host = s.level;
+  return s.beta >= 1.0 ? PHI4_DONE : PHI4_OK;
+}
+
+size_t ns_workspace_bytes(const phi4_ns_config* cfg) {
+  std::string why;
+  if (!ns_valid(cfg, &why)) return 0;
+  return ns_carve(*cfg, nullptr, nullptr);
+}
+
+int ns_init(const phi4_ns_config* cfg, float* phi, float* S, void* workspace,
+            size_t workspace_bytes, void* stream, void** handle) {
+  std::string why;
+  if (!handle) return fail(PHI4_EINVAL, "handle is NULL");
+  *handle = nullptr;
+  if (!ns_valid(cfg, &why)) return fail(PHI4_EINVAL, "ns_init: " + why);
+  if (!phi || !S) return fail(PHI4_EINVAL, "ns_init: phi / S is NULL");
+  if (!ws_ok(workspace, workspace_bytes, ns_carve(*cfg, nullptr, nullptr), &why))
+    return fail(PHI4_EINVAL, "ns_init: " + why);
+  Handle* h = new (std::nothrow) Handle();
+  if (!h) return fail(PHI4_EINVAL, "ns_init: out of host memory");
+  h->kind = 1;
+  h->stream = static_cast<hipStream_t>(stream);
+  h->phi = phi;
+  h->S = S;
+  h->L = cfg->L;
+  h->d = cfg->L * cfg->L;
+  h->n = cfg->n_live;
+  h->m2 = (float)cfg->m2;
+  h->lam = (float)cfg->lambda;
+  h->seed = cfg->seed;
+  h->run = cfg->run;
+  h->precision = cfg->precision;
+  h->n_steps = cfg->n_steps;
+  h->ns = *cfg;
+  ns_carve(*cfg, workspace, h);
+  int rc = alloc_pinned(h, sizeof(NsState));
+  if (rc) {
+    delete h;
+    return rc;
+  }
+  launch_ns_state_init(h->nst, default_eps0(h->d, cfg->eps0), cfg->acc_target, h->stream);
+  launch_init_fields(phi, S, h->absM, h->n, h->L, h->m2, h->lam, (float)std::sqrt(cfg->prior_var),
+                     h->seed, h->run, h->stream);
+  rc = hip_check("ns_init");
+  if (rc) {
+    phi4_destroy(h);
+    return rc;
+  }
+  *handle = h;
+  return PHI4_OK;
+}
+
+int ns_step(void* handle, int32_t* done_host) {
+  Handle* h = as_handle(handle, 1);
+  if (!h) return fail(PHI4_EINVAL, "ns_step: not a nested-sampling handle");
+  const NsArgs a = ns_args(h);
+  launch_ns_select(a, h->stream);
+  launch_ns_seed_copy(a, h->stream);
+  launch_cov_partials(h->phi, h->surv, h->nplan, h->part, &h->nst->done, h->stream);
+  FactorArgs fa = {};
+  fa.part = h->part;
+  fa.plan = h->nplan;
+  fa.sigma_out = h->sigma;
+  fa.A = h->A;
+  fa.Bt = h->Bt;
+  fa.ldb = h->d;
+  fa.eps_ptr = &h->nst->eps;
+  fa.tau_out = &h->nst->tau;
+  fa.err_out = &h->nst->err;
+  fa.done = &h->nst->done;
+  launch_factor(fa, h->stream);
+  MutateArgs m = {};
+  m.src = h->phi;
+  m.dst = h->phi;
+  m.rows = h->dead;
+  m.n = h->ns.k_delete;
+  m.L = h->L;
+  m.d = h->d;
+  m.m2 = h->m2;
+  m.lam = h->lam;
+  m.Bt = h->Bt;
+  m.ldb = h->d;
+  m.kind = 1;
+  m.sstar_ptr = &h->nst->s_star;
+  m.inv_prior_var = (float)(1.0 / h->ns.prior_var);
+  m.seed = h->seed;
+  m.run = h->run;
+  m.level_ptr = &h->nst->iter;
+  m.step0 = 0;
+  m.n_steps = h->n_steps;
+  m.zsign = 1.0f;
+  m.done_ptr = &h->nst->done;
+  m.S = h->S;
+  m.absM = h->absM;
+  m.acc_count = &h->nst->acc;
+  m.prop_count = &h->nst->prop;
+  int rc;
+  {
+    TimedLaunch tl(h);
+    rc = launch_mutate(m, h->precision, h->stream);
+  }
+  if (rc) return fail(rc, "ns_step: unsupported shape");
+  rc = hip_check("ns_step");
+  if (rc) return rc;
+  if (!done_host) return PHI4_OK;
+  NsState* s = static_cast<NsState*>(h->pinned);
+  rc = copy_state(h, s, sizeof(NsState), h->nst);
+  if (rc) return rc;
+  if (s->err) return state_error(s->err);
+  *done_host = s->done;
+  return s->done ? PHI4_DONE : PHI4_OK;
+}
+
+int logz(void* handle, double* logz_host, double* stderr_host) {
+  Handle* h = static_cast<Handle*>(handle);
+  if (!h || !logz_host) return fail(PHI4_EINVAL, "logz: NULL argument");
+  if (h->kind == 0) {
+    SmcState* s = static_cast<SmcState*>(h->pinned);
+    const int rc = copy_state(h, s, sizeof(SmcState), h->sb.st);
+    if (rc) return rc;
+    if (s->err) return state_error(s->err);
+    *logz_host = s->logz;
+    if (stderr_host) *stderr_host = NAN;
+    return PHI4_OK;
+  }
+  NsState* s = static_cast<NsState*>(h->pinned);
+  const int rc = copy_state(h, s, sizeof(NsState), h->nst);
+  if (rc) return rc;
+  if (s->err) return state_error(s->err);
+  *logz_host = s->logZ;
+  if (stderr_host) *stderr_host = std::sqrt(std::fmax(s->H, 0.0) / h->n);
+  return PHI4_OK;
+}
+
+int phi4_observables(void* handle, double* out) {
+  Handle* h = static_cast<Handle*>(handle);
+  if (!h || !out) return fail(PHI4_EINVAL, "phi4_observables: NULL argument");
+  if (h->kind == 0) {
+    SmcBufs& b = h->sb;
+    const float* curP = h->cur ? b.alt_phi : h->phi;
+    launch_action(curP, h->n, h->L, h->m2, h->lam, b.obs_S, b.obs_absM, h->stream);
+    launch_mean_abs(b.obs_absM, h->n, &b.st->mean_abs_m, nullptr, h->stream);
+    int rc = hip_check("phi4_observables");
+    if (rc) return rc;
+    SmcState* s = static_cast<SmcState*>(h->pinned);
+    rc = copy_state(h, s, sizeof(SmcState), b.st);
+    if (rc) return rc;
+    out[0] = s->mean_abs_m;
+    out[1] = s->beta;
+    out[2] = s->last_acc;
+    out[3] = s->eps;
+    out[4] = s->level;
+    out[5] = s->last_dbeta;
+    out[6] = s->last_ess;
+    out[7] = s->tau;
+    out[8] = s->solve_iters;
+    out[9] = s->done;
+    return PHI4_OK;
+  }
+  NsState* s = static_cast<NsState*>(h->pinned);
+  const int rc = copy_state(h, s, sizeof(NsState), h->nst);
+  if (rc) return rc;
+  out[0] = std::exp(s->logmz - s->logZ);
+  out[1] = s->logX;
+  out[2] = s->last_acc;
+  out[3] = s->eps;
+  out[4] = s->iter;
+  out[5] = s->s_star;
+  out[6] = s->H;
+  out[7] = s->tau;
+  out[8] = 0.0;
+  out[9] = s->done;
+  return PHI4_OK;
+}
+
+int phi4_set_timing(void* handle, int32_t enabled) {
+  Handle* h = static_cast<Handle*>(handle);
+  if (!h) return fail(PHI4_EINVAL, "phi4_set_timing: NULL handle");
+  h->timing = enabled != 0;
+  return PHI4_OK;
+}
+
+int phi4_kernel_time(void* handle, double* ms_host, int32_t* launches_host) {
+  Handle* h = static_cast<Handle*>(handle);
+  if (!h || !ms_host) return fail(PHI4_EINVAL, "phi4_kernel_time: NULL argument");
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  double total = 0.0;
+  for (size_t i = 0; i < h->tused; ++i) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, h->tev[i].first, h->tev[i].second));
+    total += ms;
+  }
+  *ms_host = total;
+  if (launches_host) *launches_host = (int32_t)h->tused;
+  h->tused = 0;
+  return PHI4_OK;
+}
+
+int phi4_destroy(void* handle) {
+  Handle* h = static_cast<Handle*>(handle);
+  if (!h) return PHI4_OK;
+  for (auto& p : h->tev) {
+    (void)hipEventDestroy(p.first);
+    (void)hipEventDestroy(p.second);
+  }
+  if (h->pinned) (void)hipHostFree(h->pinned);
+  if (h->ev[0]) (void)hipEventDestroy(h->ev[0]);
+  if (h->ev[1]) (void)hipEventDestroy(h->ev[1]);
+  delete h;
+  return PHI4_OK;
+}
+
+// ------------------------------------------------------------ step level
+
+size_t phi4_step_workspace_bytes(int32_t N, int32_t d) {
+  if (N < 0 || d < 0 || d > PHI4_MAX_SITES) return 0;
+  return step_carve(N, d, nullptr, nullptr);
+}
+
+int phi4_normals(uint32_t seed, uint32_t run, int32_t level, int32_t step, int32_t purpose,
+                 const int32_t* rows, int32_t n, int32_t d, float* out, void* stream) {
+  if (n < 0 || d < 1 || (n > 0 && !out)) return fail(PHI4_EINVAL, "phi4_normals: bad shape");
+  if (level < 0 || level >= (1 << 24) || purpose < 0 || purpose > 255)
+    return fail(PHI4_EINVAL, "phi4_normals: level / purpose out of range");
+  launch_normals(seed, run, level, step, purpose, rows, n, d, out, static_cast<hipStream_t>(stream));
+  return hip_check("phi4_normals");
+}
+
+int phi4_action(const float* phi, int32_t N, int32_t L, double m2, double lambda, float* S,
+                float* absM, void* stream) {
+  if (N < 0 || L < 1 || (long long)L * L > PHI4_MAX_SITES || (N > 0 && (!phi || !S)))
+    return fail(PHI4_EINVAL, "phi4_action: bad shape");
+  launch_action(phi, N, L, (float)m2, (float)lambda, S, absM, static_cast<hipStream_t>(stream));
+  return hip_check("phi4_action");
+}
+
+int phi4_resample_systematic(const double* w, int32_t N, uint32_t U, int32_t* ancestors,
+                             void* workspace, size_t workspace_bytes, void* stream) {
+  std::string why;
+  if (N < 0 || (N > 0 && (!w || !ancestors))) return fail(PHI4_EINVAL, "phi4_resample_systematic: bad shape");
+  if (N == 0) return PHI4_OK;
+  if (!ws_ok(workspace, workspace_bytes, step_carve(N, 1, nullptr, nullptr), &why))
+    return fail(PHI4_EINVAL, "phi4_resample_systematic: " + why);
+  StepBufs b;
+  step_carve(N, 1, workspace, &b);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  launch_resample_weights(w, N, U, b.cdf, b.marks, ancestors, b.status, s);
+  int rc = hip_check("phi4_resample_systematic");
+  if (rc) return rc;
+  int32_t status = 0;
+  HIP_TRY(hipMemcpyAsync(&status, b.status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (status) return fail(status, "phi4_resample_systematic: weights must be finite, >= 0, max > 0");
+  return PHI4_OK;
+}
+
+int phi4_reweight(const float* S, int32_t N, double beta, double ess_frac, double* w,
+                  double* out_host, void* workspace, size_t workspace_bytes, void* stream) {
+  std::string why;
+  if (N < 1 || !S || !out_host) return fail(PHI4_EINVAL, "phi4_reweight: bad arguments");
+  if (!(beta >= 0.0 && beta < 1.0) || !(ess_frac > 0.0 && ess_frac <= 1.0))
+    return fail(PHI4_EINVAL, "phi4_reweight: need 0 <= beta < 1 and 0 < ess_frac <= 1");
+  if (!ws_ok(workspace, workspace_bytes, step_carve(N, 1, nullptr, nullptr), &why))
+    return fail(PHI4_EINVAL, "phi4_reweight: " + why);
+  StepBufs b;
+  step_carve(N, 1, workspace, &b);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ReweightArgs ra = {};
+  ra.S = S;
+  ra.n = N;
+  ra.st = nullptr;
+  ra.beta_in = beta;
+  ra.ess_frac_in = ess_frac;
+  ra.out = b.out;
+  ra.w = w;
+  ra.do_resample = 0;
+  launch_reweight(ra, s);
+  int rc = hip_check("phi4_reweight");
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(out_host, b.out, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (!std::isfinite(out_host[0])) return fail(PHI4_ENONFINITE, "phi4_reweight: non-finite actions or stalled solve");
+  return PHI4_OK;
+}
+
+int phi4_covariance(const float* phi, const int32_t* rows, int32_t N, int32_t d, double* sigma,
+                    void* workspace, size_t workspace_bytes, void* stream) {
+  std::string why;
+  if (N < 2 || d < 1 || d > PHI4_MAX_SITES || !phi || !sigma)
+    return fail(PHI4_EINVAL, "phi4_covariance: need N >= 2, 1 <= d <= 256");
+  if (!ws_ok(workspace, workspace_bytes, step_carve(N, d, nullptr, nullptr), &why))
+    return fail(PHI4_EINVAL, "phi4_covariance: " + why);
+  StepBufs b;
+  step_carve(N, d, workspace, &b);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const CovPlan plan = cov_plan(N, d);
+  launch_cov_partials(phi, rows, plan, b.part, nullptr, s);
+  FactorArgs fa = {};
+  fa.part = b.part;
+  fa.plan = plan;
+  fa.sigma_out = sigma;
+  fa.A = b.A;
+  fa.cov_only = 1;
+  launch_factor(fa, s);
+  return hip_check("phi4_covariance");
+}
+
+int phi4_cholesky(const double* sigma, int32_t d, double* L, double* tau_host, void* workspace,
+                  size_t workspace_bytes, void* stream) {
+  std::string why;
+  if (d < 1 || d > PHI4_MAX_SITES || !sigma || !L) return fail(PHI4_EINVAL, "phi4_cholesky: bad shape");
+  if (!ws_ok(workspace, workspace_bytes, step_carve(2, d, nullptr, nullptr), &why))
+    return fail(PHI4_EINVAL, "phi4_cholesky: " + why);
+  StepBufs b;
+  step_carve(2, d, workspace, &b);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipMemsetAsync(b.status, 0, sizeof(int32_t), s));
+  FactorArgs fa = {};
+  fa.plan = cov_plan(2, d);
+  fa.sigma_in = sigma;
+  fa.sigma_out = b.sigma;
+  fa.A = L;
+  fa.tau_out = b.tau;
+  fa.err_out = b.status;
+  launch_factor(fa, s);
+  int rc = hip_check("phi4_cholesky");
+  if (rc) return rc;
+  int32_t status = 0;
+  double tau = 0;
+  HIP_TRY(hipMemcpyAsync(&status, b.status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&tau, b.tau, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (status) return fail(status, "phi4_cholesky: not positive definite after jitter");
+  if (tau_host) *tau_host = tau;
+  return PHI4_OK;
+}
+
+int phi4_mutate(const float* src, float* dst, const int32_t* rows, int32_t n, int32_t L, double m2,
+                double lambda, const float* Bt, int32_t kind, double beta, double s_star,
+                double prior_var, uint32_t seed, uint32_t run, int32_t level, int32_t step0,
+                int32_t n_steps, float zsign, int32_t precision, float* S, float* absM,
+                unsigned long long* acc_count, uint8_t* acc_flags, float* prop, void* stream) {
+  const long long d = (long long)L * L;
+  if (n < 0 || L < 1 || d > PHI4_MAX_SITES || n_steps < 0 || (kind != 0 && kind != 1))
+    return fail(PHI4_EINVAL, "phi4_mutate: bad shape or kind");
+  if (n > 0 && (!src || !dst || !Bt || !S)) return fail(PHI4_EINVAL, "phi4_mutate: NULL buffer");
+  if (kind == 1 && !(prior_var > 0.0)) return fail(PHI4_EINVAL, "phi4_mutate: prior_var must be > 0");
+  if (level < 0 || level >= (1 << 24)) return fail(PHI4_EINVAL, "phi4_mutate: level out of range");
+  if (!mutate_supported((int)d, precision)) return fail(PHI4_EINVAL, "phi4_mutate: unsupported precision");
+  MutateArgs m = {};
+  m.src = src;
+  m.dst = dst;
+  m.rows = rows;
+  m.n = n;
+  m.L = L;
+  m.d = (int)d;
+  m.m2 = (float)m2;
+  m.lam = (float)lambda;
+  m.Bt = Bt;
+  m.ldb = (int)d;
+  m.kind = kind;
+  m.beta = (float)beta;
+  m.s_star = (float)s_star;
+  m.inv_prior_var = kind == 1 ? (float)(1.0 / prior_var) : 0.f;
+  m.seed = seed;
+  m.run = run;
+  m.level = level;
+  m.step0 = step0;
+  m.n_steps = n_steps;
+  m.zsign = zsign;
+  m.S = S;
+  m.absM = absM;
+  m.acc_count = acc_count;
+  m.acc_flags = acc_flags;
+  m.prop = prop;
+  const int rc = launch_mutate(m, precision, static_cast<hipStream_t>(stream));
+  if (rc) return fail(rc, "phi4_mutate: unsupported shape");
+  return hip_check("phi4_mutate");
+}
+
+}  // extern "C"

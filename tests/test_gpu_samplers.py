@@ -1,0 +1,74 @@
+"""Full SMC and nested-sampling runs through the C ABI against the oracle.
+
+Same seeds on both sides drive the same Philox streams, so the GPU run and
+the oracle run are coupled: they take the same decisions except at float32
+near-ties, and their log Z agree far inside the statistical error.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import exact
+from oracle import ns as ons
+from oracle import smc as osmc
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2511_15196_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_smc(L, N, m2, lam, ess, steps, seed, precision="fp32"):
+    run = P.SMC(L, N, m2, lam, ess_frac=ess, n_steps=steps, seed=seed, precision=precision)
+    rc, levels = run.run()
+    obs = run.observables()
+    z = run.logz()
+    run.close()
+    return dict(logz=z, levels=levels, mean_abs_m=obs["mean_abs_m"], acc=obs["acc"], rc=rc)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_smc_small_coupled_to_oracle(seed):
+    say("smc L=4 N=256 seed", seed)
+    g = gpu_smc(4, 256, -4.0, 8.0, 0.5, 10, seed)
+    o = osmc.smc_run(4, -4.0, 8.0, 256, 0.5, 10, seed=seed)
+    say("gpu", g, "oracle", o["logz"], o["n_levels"], o["mean_abs_m"])
+    assert g["rc"] == P.PHI4_DONE
+    assert g["levels"] == o["n_levels"]
+    assert abs(g["logz"] - o["logz"]) < 0.05
+    assert abs(g["mean_abs_m"] - o["mean_abs_m"]) < 0.01
+
+
+def test_smc_free_2x2_exact():
+    zs = [gpu_smc(2, 4096, 1.0, 0.0, 0.5, 20, s)["logz"] for s in range(8)]
+    m, se = np.mean(zs), np.std(zs, ddof=1) / math.sqrt(len(zs))
+    say("free 2x2", m, se, exact.free_logz(2, 1.0))
+    assert abs(m - exact.free_logz(2, 1.0)) < 3 * se + 0.005
+
+
+def test_smc_interacting_2x2_quadrature():
+    zs = [gpu_smc(2, 4096, -4.0, 8.0, 0.5, 20, s)["logz"] for s in range(8)]
+    m, se = np.mean(zs), np.std(zs, ddof=1) / math.sqrt(len(zs))
+    say("2x2 interacting", m, se, exact.logz_2x2(-4.0, 8.0))
+    assert abs(m - exact.logz_2x2(-4.0, 8.0)) < 3 * se + 0.005
+
+
+def test_ns_small_coupled_to_oracle():
+    say("ns L=2")
+    run = P.NS(2, 400, 200, 20, 1.0, 0.0, prior_var=4.0, term_frac=1e-3, seed=3)
+    z, se = run.run()
+    obs = run.observables()
+    run.close()
+    o = ons.ns_run(2, 1.0, 0.0, 400, 200, 20, seed=3)
+    say("gpu", z, se, obs, "oracle", o["logz"], o["logz_err"], o["n_iter"])
+    assert int(obs["levels"]) == o["n_iter"]
+    assert abs(z - o["logz"]) < 0.05
+    assert abs(se - o["logz_err"]) < 0.2 * o["logz_err"]
