@@ -137,24 +137,33 @@ __device__ __forceinline__ float wave_sum_f(float v) {
   return (r0 + r1) + (r2 + r3);
 }
 
-// Workgroup reduction.  `sh` needs blockDim/64 doubles of LDS (at most 16
-// waves).  Every thread gets the result.
-template <int OP>
+// Workgroup reductions for NW waves (blockDim = 64 NW).  The per-wave
+// results go through LDS; with at most 8 waves every thread sums them in
+// wave order, otherwise they are reduced once more like a wave.  `sh` needs
+// NW doubles (block_reduce) or 4 NW doubles (block_sum4).  Every thread gets
+// the result.
+template <int OP, int NW>
 __device__ __forceinline__ double block_reduce(double v, double* sh) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   v = wave_red<OP>(v);
   __syncthreads();
   if (lane == 0) sh[wid] = v;
   __syncthreads();
-  const double x = lane < nw ? sh[lane] : red_identity<OP>();
-  return wave_red<OP>(x);
+  if constexpr (NW <= 8) {
+    double r = sh[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) r = red_op<OP>(r, sh[w]);
+    return r;
+  } else {
+    const double x = lane < NW ? sh[lane] : red_identity<OP>();
+    return wave_red<OP>(x);
+  }
 }
 
-// Workgroup sum of four doubles at once (one pair of barriers); `sh` needs
-// 4 * blockDim/64 doubles.  Every thread gets the results.
+template <int NW>
 __device__ __forceinline__ void block_sum4(double& a, double& b, double& c, double& e,
                                            double* sh) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   a = wave_red<kSum>(a);
   b = wave_red<kSum>(b);
   c = wave_red<kSum>(c);
@@ -162,16 +171,30 @@ __device__ __forceinline__ void block_sum4(double& a, double& b, double& c, doub
   __syncthreads();
   if (lane == 0) {
     sh[wid] = a;
-    sh[16 + wid] = b;
-    sh[32 + wid] = c;
-    sh[48 + wid] = e;
+    sh[NW + wid] = b;
+    sh[2 * NW + wid] = c;
+    sh[3 * NW + wid] = e;
   }
   __syncthreads();
-  const bool in = lane < nw;
-  a = wave_red<kSum>(in ? sh[lane] : 0.0);
-  b = wave_red<kSum>(in ? sh[16 + lane] : 0.0);
-  c = wave_red<kSum>(in ? sh[32 + lane] : 0.0);
-  e = wave_red<kSum>(in ? sh[48 + lane] : 0.0);
+  if constexpr (NW <= 8) {
+    a = sh[0];
+    b = sh[NW];
+    c = sh[2 * NW];
+    e = sh[3 * NW];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      a += sh[w];
+      b += sh[NW + w];
+      c += sh[2 * NW + w];
+      e += sh[3 * NW + w];
+    }
+  } else {
+    const bool in = lane < NW;
+    a = wave_red<kSum>(in ? sh[lane] : 0.0);
+    b = wave_red<kSum>(in ? sh[NW + lane] : 0.0);
+    c = wave_red<kSum>(in ? sh[2 * NW + lane] : 0.0);
+    e = wave_red<kSum>(in ? sh[3 * NW + lane] : 0.0);
+  }
 }
 
 // --------------------------------------------------------------- states

@@ -11,12 +11,15 @@
 // float32 products at the scale of the spread.
 //
 // Factor: tau = 1e-10 tr(Sigma) / d is added to the diagonal and multiplied
-// by 100 after each failed factorisation (at most five retries).  The
-// factorisation is right-looking in 64-column panels: the diagonal block is
-// factorised in LDS in outer-product form (one barrier per column), the panel
-// below it is solved row by row and the trailing matrix updated from LDS.
-// The scaled factor is emitted transposed in float32 for the mutation
-// kernel: Bt[k*d + c] = eps * L[c][k].
+// by 100 after each failed factorisation (at most five retries).  For
+// d <= 64 one wave factorises in registers (lane i owns row i, right-looking
+// outer-product sweep, column broadcast through LDS, no workgroup barriers);
+// larger d is factorised right-looking in 64-column panels: the diagonal
+// block in LDS in outer-product form, the panel below it solved row by row
+// and the trailing matrix updated from LDS.  The scaled factor is emitted
+// transposed in float32 for the mutation kernel: Bt[k*d + c] = eps * L[c][k].
+#include <utility>
+
 #include "common.hpp"
 
 namespace phi4 {
@@ -241,7 +244,7 @@ __global__ __launch_bounds__(kFT) void factor_kernel(FactorArgs a) {
   if (a.cov_only) return;
   double tr = 0.0;
   for (int i = threadIdx.x; i < d; i += kFT) tr += sig[(size_t)i * d + i];
-  tr = block_reduce<kSum>(tr, shd);
+  tr = block_reduce<kSum, 16>(tr, shd);
   double tau = 1e-10 * tr / d;
   bool ok = false;
   for (int attempt = 0; attempt < 6 && !ok; ++attempt) {
@@ -275,107 +278,152 @@ __global__ __launch_bounds__(kFT) void factor_kernel(FactorArgs a) {
 
 constexpr int kSmallD = 64;
 
-// Owner-computes Cholesky for d <= 64 with 256 threads: thread t owns column
-// j = t mod 64 and rows i = t / 64 + 4q (q < 16) of the matrix, in registers.
-// Outer-product form without square roots during the sweep: at step k the
-// current column k is broadcast through LDS (double buffered) and every
-// owner applies D[i][j] -= D[i][k] D[j][k] / D[k][k] for k < j <= i;
-// afterwards L[i][j] = D[i][j] / sqrt(D[j][j]).  One barrier per column.
-__global__ __launch_bounds__(256) void factor_small_kernel(FactorArgs a) {
-  if (a.done && *a.done) return;
-  __shared__ double col[2][kSmallD];
-  __shared__ double piv[kSmallD];
-  __shared__ double shd[64];
-  const CovPlan& p = a.plan;
-  const int d = p.d, tid = threadIdx.x;
-  const int j = tid & 63, i0 = tid >> 6;
-  double* sig = a.sigma_out;
-  const double* src = a.sigma_in ? a.sigma_in : sig;
-  const bool jv = j < d;
-  double v[16];
-  auto load = [&]() {
+// One-wave Cholesky for d <= D (D = 16, 32 or 64): lane i keeps row i of the
+// matrix in registers, padded to D x D with the identity (the padding stays
+// the identity and factors to itself).  Right-looking outer-product form: at
+// step k every lane publishes its entry of column k through LDS, and lane i
+// applies D[i][j] -= (D[i][k] / D[k][k]) D[j][k] for j > k, then keeps
+// L[i][k] = D[i][k] / sqrt(D[k][k]) (sqrt(D[k][k]) on the diagonal, 0 above
+// it).  Column k + 1 is updated and published first so that its LDS round
+// trip overlaps the rest of step k.  Entries above the diagonal are carried
+// along unused until their own step zeroes them.
+// 1 / p in float64: hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double recip_f64(double p) {
+  double r = __builtin_amdgcn_rcp(p);
+  double e = fma(-p, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-p, r, 1.0);
+  return fma(r, e, r);
+}
+
+// Step K of the one-wave sweep below (all indices compile-time constants).
+// On entry v[K] holds D[i][K], column K sits in col[K & 1] and rp = 1/D[K][K].
+// Column K + 1 is updated first and published through LDS for the next step;
+// its pivot D[K+1][K+1] is read straight from lane K + 1's register, so the
+// next reciprocal overlaps the remaining updates of step K.
+template <int D, int K>
+__device__ __forceinline__ void chol_wave_step(double (&v)[D], double (*col)[64], int i,
+                                               double& rp, double& pown, bool& bad) {
+  constexpr int kC = 8;                       // column entries per LDS chunk
+  constexpr int m0 = (K + 2) / kC, m1 = D / kC;
+  const double* ck = col[K & 1];
+  const double f = v[K] * rp;
+  if constexpr (K + 1 < D) {
+    v[K + 1] = fma(-f, ck[K + 1], v[K + 1]);
+    col[(K + 1) & 1][i] = v[K + 1];
+    __builtin_amdgcn_sched_barrier(0);        // keep the publish ahead of the updates
+    pown = i == K + 1 ? v[K + 1] : pown;      // lane K + 1 keeps its pivot
+    const double pn = readlane64(v[K + 1], K + 1);
+    bad |= !(pn > 0.0) | isinf(pn);
+    rp = recip_f64(pn);
+  }
+  double cb[2][kC];
+  if constexpr (m0 < m1) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int i = i0 + 4 * q;
-      const double x = src[(size_t)min(i, d - 1) * d + min(j, d - 1)];   // valid address
-      v[q] = (jv && i < d) ? x : 0.0;
+    for (int t = 0; t < kC; ++t) cb[0][t] = ck[m0 * kC + t];
+  }
+#pragma unroll
+  for (int m = m0; m < m1; ++m) {
+    if (m + 1 < m1) {
+#pragma unroll
+      for (int t = 0; t < kC; ++t) cb[(m + 1 - m0) & 1][t] = ck[(m + 1) * kC + t];
     }
-  };
-  load();
-  if (a.sigma_in) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int i = i0 + 4 * q;
-      if (jv && i < d) sig[(size_t)i * d + j] = v[q];
+    for (int t = 0; t < kC; ++t) {
+      const int j = m * kC + t;
+      if (j >= K + 2) v[j] = fma(-f, cb[(m - m0) & 1][t], v[j]);
     }
   }
-  if (a.cov_only) return;
-  double tr = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
+  __syncthreads();                            // one wave: orders the column exchange
+}
+
+template <int D, int... K>
+__device__ __forceinline__ void chol_wave_sweep(double (&v)[D], double (*col)[64], int i,
+                                                double& rp, double& pown, bool& bad,
+                                                std::integer_sequence<int, K...>) {
+  (chol_wave_step<D, K>(v, col, i, rp, pown, bad), ...);
+}
+
+// One-wave Cholesky for d <= D (D = 16, 32 or 64): lane i keeps row i of the
+// matrix in registers, padded to D x D with the identity (the padding stays
+// the identity and factors to itself).  Right-looking outer-product sweep
+// without square roots: at step K lane i applies
+// D[i][j] -= (D[i][K] / D[K][K]) D[j][K] for j > K, with column K broadcast
+// through LDS; column K + 1 is updated and published first, and the next
+// pivot is read from its lane's register, so the next reciprocal overlaps
+// the rest of step K.  At the
+// end L[i][j] = D[i][j] / sqrt(D[j][j]) below the diagonal and
+// L[i][i] = sqrt(D[i][i]), D[j][j] being the pivot of step j.  Entries above
+// the diagonal are carried along unused.
+template <int D>
+__global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
+  if (a.done && *a.done) return;
+  __shared__ double M[D][D + 1];   // the matrix padded with the identity
+  __shared__ double col[2][64];
+  const int d = a.plan.d;
+  const int i = threadIdx.x;
+  const bool rv = i < d;
+  double* sig = a.sigma_out;
+  const double* src = a.sigma_in ? a.sigma_in : sig;
+  // stage the matrix (clamped valid addresses, all loads of a batch in flight)
+  constexpr int kPer = D * D / 64;                // entries per lane
+  constexpr int kB = kPer < 16 ? kPer : 16;       // loads in flight
 #pragma unroll
-  for (int q = 0; q < 16; ++q)
-    if (jv && i0 + 4 * q == j) tr += v[q];
-  block_sum4(tr, z1, z2, z3, shd);
+  for (int b = 0; b < kPer; b += kB) {
+    double x[kB];
+#pragma unroll
+    for (int q = 0; q < kB; ++q) {
+      const int e = (b + q) * 64 + i, r = e / D, cc = e % D;
+      x[q] = src[(size_t)min(r, d - 1) * d + min(cc, d - 1)];
+    }
+#pragma unroll
+    for (int q = 0; q < kB; ++q) {
+      const int e = (b + q) * 64 + i, r = e / D, cc = e % D;
+      const bool in = r < d && cc < d;
+      M[r][cc] = in ? x[q] : (r == cc ? 1.0 : 0.0);
+      if (a.sigma_in && in) sig[(size_t)r * d + cc] = x[q];
+    }
+  }
+  __syncthreads();
+  const int ir = min(i, D - 1);   // lanes beyond D mirror row D - 1, unused
+  const double tr = wave_red<kSum>(rv ? M[ir][ir] : 0.0);
   double tau = 1e-10 * tr / d;
+  double v[D], pown = 1.0;
   bool ok = false;
   for (int attempt = 0; attempt < 6 && !ok; ++attempt) {
-    if (attempt) {
-      tau *= 100.0;
-      load();
-    }
+    if (attempt) tau *= 100.0;
+    // row i plus tau on the diagonal
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int i = i0 + 4 * q;
-      if (jv && i == j) v[q] += tau;
-      if (j == 0 && i < d) col[0][i] = v[q];
-    }
+    for (int j = 0; j < D; ++j) v[j] = M[ir][j] + ((rv && i == j) ? tau : 0.0);
+    pown = i == 0 ? v[0] : 1.0;
+    col[0][i] = v[0];
     __syncthreads();
-    ok = true;
-    for (int k = 0; k < d; ++k) {
-      const int cb = k & 1;
-      const double dkk = col[cb][k];
-      if (!(dkk > 0.0) || isinf(dkk)) {
-        ok = false;
-        break;
-      }
-      if (tid == 0) piv[k] = dkk;
-      if (jv && j > k) {
-        const double cj = col[cb][j] / dkk;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          const int i = i0 + 4 * q;
-          if (i >= j && i < d) v[q] -= col[cb][i] * cj;
-        }
-        if (j == k + 1) {
-#pragma unroll
-          for (int q = 0; q < 16; ++q) {
-            const int i = i0 + 4 * q;
-            if (i >= j && i < d) col[cb ^ 1][i] = v[q];   // next column, final now
-          }
-        }
-      }
-      __syncthreads();
-    }
+    const double p0 = readlane64(v[0], 0);
+    bool bad = !(p0 > 0.0) | isinf(p0);
+    double rp = recip_f64(p0);
+    chol_wave_sweep<D>(v, col, i, rp, pown, bad, std::make_integer_sequence<int, D>{});
+    ok = !bad;
     __syncthreads();
   }
   if (!ok) {
-    if (tid == 0 && a.err_out) *a.err_out = PHI4_ECHOL;
+    if (i == 0 && a.err_out) *a.err_out = PHI4_ECHOL;
     return;
   }
-  if (!jv) return;
+  // 1 / sqrt(pivot j) from lane j, broadcast through LDS
+  const double sq = sqrt(pown);
+  col[0][i] = 1.0 / sq;
+  __syncthreads();
+  if (!rv) return;
   const double eps = a.Bt ? *a.eps_ptr : 0.0;
-  const double rj = 1.0 / sqrt(piv[j]);
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int i = i0 + 4 * q;
-    if (i >= d) continue;
-    double l = 0.0;
-    if (j < i) l = v[q] * rj;
-    else if (j == i) l = sqrt(piv[i]);
-    a.A[(size_t)i * d + j] = l;
-    // Bt[k][c] = eps L[c][k]: this entry is L[i][j] -> Bt[j][i]
-    if (a.Bt) a.Bt[(size_t)j * a.ldb + i] = (j <= i) ? (float)(eps * l) : 0.f;
-  }
-  if (tid == 0 && a.tau_out) *a.tau_out = tau;
+  for (int j = 0; j < D; ++j)
+    if (j < d) {
+      const double l = j < i ? v[j] * col[0][j] : (j == i ? sq : 0.0);
+      a.A[(size_t)i * d + j] = l;
+      // Bt[k][c] = eps L[c][k]: this entry is L[i][j] -> Bt[j][i]
+      if (a.Bt) a.Bt[(size_t)j * a.ldb + i] = (float)(eps * l);
+    }
+  if (i == 0 && a.tau_out) *a.tau_out = tau;
 }
 
 }  // namespace
@@ -416,8 +464,12 @@ void launch_factor(const FactorArgs& a, hipStream_t s) {
     cov_reduce_kernel<<<(entries + 255) / 256, 256, 0, s>>>(a.part, a.plan, a.sigma_out, a.done);
   }
   if (a.cov_only) return;
-  if (a.plan.d <= kSmallD)
-    factor_small_kernel<<<1, 256, 0, s>>>(a);
+  if (a.plan.d <= 16)
+    factor_wave_kernel<16><<<1, 64, 0, s>>>(a);
+  else if (a.plan.d <= 32)
+    factor_wave_kernel<32><<<1, 64, 0, s>>>(a);
+  else if (a.plan.d <= kSmallD)
+    factor_wave_kernel<kSmallD><<<1, 64, 0, s>>>(a);
   else
     factor_kernel<<<1, kFT, 0, s>>>(a);
 }

@@ -59,16 +59,16 @@ __device__ void ns_add_live(const NsArgs& a, double* shd) {
     lmax = fmax(lmax, lw);
     mmax = fmax(mmax, lw + log((double)a.absM[i]));
   }
-  lmax = block_reduce<kMax>(lmax, shd);
-  mmax = block_reduce<kMax>(mmax, shd);
+  lmax = block_reduce<kMax, 16>(lmax, shd);
+  mmax = block_reduce<kMax, 16>(mmax, shd);
   double sw = 0.0, sm = 0.0;
   for (int i = threadIdx.x; i < n; i += kNT) {
     const double lw = logX - log((double)n) - (double)a.S[i];
     sw += exp(lw - lmax);
     if (mmax > -INFINITY) sm += exp(lw + log((double)a.absM[i]) - mmax);
   }
-  sw = block_reduce<kSum>(sw, shd);
-  sm = block_reduce<kSum>(sm, shd);
+  sw = block_reduce<kSum, 16>(sw, shd);
+  sm = block_reduce<kSum, 16>(sm, shd);
   const double lz_live = lmax + log(sw);
   const double logZ = lse2(logZ0, lz_live);
   double hs = 0.0;
@@ -76,7 +76,7 @@ __device__ void ns_add_live(const NsArgs& a, double* shd) {
     const double lw = logX - log((double)n) - (double)a.S[i];
     hs += exp(lw - logZ) * (-(double)a.S[i]);
   }
-  hs = block_reduce<kSum>(hs, shd);
+  hs = block_reduce<kSum, 16>(hs, shd);
   __syncthreads();
   if (threadIdx.x == 0) {
     const double hsum = (logZ0 > -INFINITY ? st->hsum * exp(logZ0 - logZ) : 0.0) + hs;
@@ -108,10 +108,10 @@ __global__ __launch_bounds__(kNT) void ns_select_kernel(NsArgs a) {
   if (st->logZ > -INFINITY) {
     double lmax = -INFINITY;
     for (int i = threadIdx.x; i < n; i += kNT) lmax = fmax(lmax, -(double)a.S[i]);
-    lmax = block_reduce<kMax>(lmax, shd);
+    lmax = block_reduce<kMax, 16>(lmax, shd);
     double s = 0.0;
     for (int i = threadIdx.x; i < n; i += kNT) s += exp(-(double)a.S[i] - lmax);
-    s = block_reduce<kSum>(s, shd);
+    s = block_reduce<kSum, 16>(s, shd);
     const double live = st->logX + lmax + log(s) - log((double)n);
     if (live - st->logZ < log(a.term_frac)) {
       ns_add_live(a, shd);
@@ -163,23 +163,23 @@ __global__ __launch_bounds__(kNT) void ns_select_kernel(NsArgs a) {
     lmax = fmax(lmax, v);
     mmax = fmax(mmax, v + log((double)a.absM[r]));
   }
-  lmax = block_reduce<kMax>(lmax, shd);
-  mmax = block_reduce<kMax>(mmax, shd);
+  lmax = block_reduce<kMax, 16>(lmax, shd);
+  mmax = block_reduce<kMax, 16>(mmax, shd);
   double sw = 0.0, sm = 0.0;
   for (int j = threadIdx.x; j < k; j += kNT) {
     const int r = (int)(keys[j] & 0xFFFFFFFFull);
     sw += exp(lw[j] - lmax);
     if (mmax > -INFINITY) sm += exp(lw[j] + log((double)a.absM[r]) - mmax);
   }
-  sw = block_reduce<kSum>(sw, shd);
-  sm = block_reduce<kSum>(sm, shd);
+  sw = block_reduce<kSum, 16>(sw, shd);
+  sm = block_reduce<kSum, 16>(sm, shd);
   const double logZ = lse2(logZ0, lmax + log(sw));
   double hs = 0.0;
   for (int j = threadIdx.x; j < k; j += kNT) {
     const int r = (int)(keys[j] & 0xFFFFFFFFull);
     hs += exp(lw[j] - logZ) * (-(double)a.S[r]);
   }
-  hs = block_reduce<kSum>(hs, shd);
+  hs = block_reduce<kSum, 16>(hs, shd);
   // ---- row lists
   for (int j = threadIdx.x; j < n; j += kNT) {
     const int r = (int)(keys[j] & 0xFFFFFFFFull);

@@ -4,10 +4,10 @@
 //
 // The tempering increment solves ESS(dbeta) = ess_frac * N with
 // ESS = (sum w)^2 / sum w^2, w_i = exp(-dbeta (S_i - S_min)), by a
-// bracketed Newton iteration on g = log ESS - log target; the returned
-// increment is the lower end of a bracket of relative width <= 1e-13, so
-// ESS(dbeta) >= target always holds (the adaptive SMC rule of App. A with
-// the target ESS of the configuration).
+// bracketed float64 Newton iteration on g = log ESS - log target, started
+// from a float32 Newton pre-solve; the returned increment is the lower end of
+// a bracket of relative width <= 1e-13, so ESS(dbeta) >= target always holds
+// (the adaptive SMC rule of App. A with the target ESS of the configuration).
 //
 // Systematic resampling (positions (i + U/2^32) / N of the normalised CDF)
 // is evaluated on integer weights q_i = floor(2^k w_i / max w),
@@ -23,31 +23,19 @@ namespace phi4 {
 
 namespace {
 
-constexpr int kRT = 1024;  // threads of the single-workgroup kernels
+constexpr int kRT = 512;                 // threads of the single-workgroup kernels
+constexpr int kNW = kRT / 64;            // waves
+constexpr int kSeg = 32;                 // particles per thread on the register path
+constexpr int kRegN = kRT * kSeg;        // largest N on the register path (16384)
 
 struct Sums {
   double a, b, da, db;  // sum e, sum e^2, d/dx sum e, d/dx sum e^2
 };
 
-// e_i = exp(l_i - max l) with l_i = -x S_i and max l = -x smin
-__device__ Sums ess_sums(const float* __restrict__ S, int n, double x, double smin, double* sh) {
-  const double mx = -x * smin;
-  double a = 0, b = 0, da = 0, db = 0;
-  for (int i = threadIdx.x; i < n; i += kRT) {
-    const double si = (double)S[i];
-    const double e = exp(-x * si - mx);
-    const double sd = si - smin;
-    a += e;
-    b += e * e;
-    da -= sd * e;
-    db -= 2.0 * sd * e * e;
-  }
-  block_sum4(a, b, da, db, sh);
-  return Sums{a, b, da, db};
-}
+// ---------------------------------------------------------------- scans
 
 __device__ unsigned long long block_excl_scan_u64(unsigned long long v, unsigned long long* sh) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   unsigned long long x = v;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -58,8 +46,9 @@ __device__ unsigned long long block_excl_scan_u64(unsigned long long v, unsigned
   if (lane == 63) sh[wid] = x;
   __syncthreads();
   unsigned long long off = 0;
-  for (int w = 0; w < wid; ++w) off += sh[w];
-  (void)nw;
+#pragma unroll
+  for (int w = 0; w < kNW; ++w)
+    if (w < wid) off += sh[w];
   return off + x - v;
 }
 
@@ -76,89 +65,44 @@ __device__ int block_excl_scan_max(int v, int* sh) {
   if (lane == 63) sh[wid] = x;
   __syncthreads();
   int off = 0;
-  for (int w = 0; w < wid; ++w) off = max(off, sh[w]);
+#pragma unroll
+  for (int w = 0; w < kNW; ++w)
+    if (w < wid) off = max(off, sh[w]);
   return lane == 0 ? off : max(off, ex);
 }
 
+// #{i : T_i < C} = min(n, ceil((C n - off) / Q)) in exact integers: a
+// float64 estimate of the quotient (relative error ~1e-16, so off by at most
+// one for quotients below 2^52) corrected with exact products; every product
+// stays below 2^63 because C <= Q <= n 2^k and n^2 2^k <= 2^62.
 __device__ __forceinline__ long long count_below(unsigned long long C, unsigned long long Q,
                                                  unsigned long long off, int n) {
   const unsigned long long cn = C * (unsigned long long)n;
   if (cn <= off) return 0;
-  const unsigned long long c = (cn - off + Q - 1) / Q;
+  const unsigned long long num = cn - off;
+  unsigned long long c = (unsigned long long)ceil((double)num / (double)Q);
+  if (c > (unsigned long long)n + 1) c = (unsigned long long)n + 1;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    if (c * Q < num) ++c;                       // too small
+    else if (c > 0 && (c - 1) * Q >= num) --c;  // too large
+  }
   return c < (unsigned long long)n ? (long long)c : (long long)n;
 }
 
-// Systematic resampling of w[0..n) (finite, >= 0, max > 0) with offset word
-// U.  Scratch: cdf[n] (uint64), marks[n] (int).  Writes anc[n].  Returns
-// 0, or PHI4_ENONFINITE for invalid weights (uniform across the block).
-__device__ int resample_block(const double* __restrict__ w, int n, uint32_t U,
-                              unsigned long long* __restrict__ cdf, int32_t* __restrict__ marks,
-                              int32_t* __restrict__ anc, double* shd,
-                              unsigned long long* shu, int* shi) {
-  // validity and max
-  double wmax = -1.0, bad = 0.0;
-  for (int i = threadIdx.x; i < n; i += kRT) {
-    const double x = w[i];
-    if (!(x >= 0.0) || isinf(x)) bad = 1.0;
-    wmax = fmax(wmax, x);
-  }
-  bad = block_reduce<kMax>(bad, shd);
-  wmax = block_reduce<kMax>(wmax, shd);
-  if (bad != 0.0 || !(wmax > 0.0)) return PHI4_ENONFINITE;
-  const int k = n > 1 ? 62 - 2 * (32 - __clz((unsigned)(n - 1))) : 62;
-  // contiguous segment per thread
-  const int per = (n + kRT - 1) / kRT;
-  const int i0 = min(n, (int)threadIdx.x * per), i1 = min(n, i0 + per);
-  unsigned long long loc = 0;
-  for (int i = i0; i < i1; ++i) {
-    const unsigned long long q = (unsigned long long)floor(ldexp(w[i] / wmax, k));
-    loc += q;
-    cdf[i] = loc;
-  }
-  const unsigned long long ex = block_excl_scan_u64(loc, shu);
-  for (int i = i0; i < i1; ++i) cdf[i] += ex;
-  for (int i = threadIdx.x; i < n; i += kRT) marks[i] = 0;
-  __syncthreads();
-  const unsigned long long Q = cdf[n - 1];
-  const unsigned long long uu = (unsigned long long)U;
-  const unsigned long long off = uu * (Q >> 32) + ((uu * (Q & 0xFFFFFFFFull)) >> 32);
-  for (int j = i0; j < i1; ++j) {
-    const unsigned long long cprev = j ? cdf[j - 1] : 0ull;
-    const long long lo = count_below(cprev, Q, off, n);
-    const long long hi = count_below(cdf[j], Q, off, n);
-    if (hi > lo) marks[lo] = j + 1;
-  }
-  __syncthreads();
-  int mloc = 0;
-  for (int i = i0; i < i1; ++i) mloc = max(mloc, marks[i]);
-  int run = block_excl_scan_max(mloc, shi);
-  for (int i = i0; i < i1; ++i) {
-    run = max(run, marks[i]);
-    anc[i] = run - 1;
-  }
-  __syncthreads();
-  return 0;
+__device__ __forceinline__ int resample_bits(int n) {
+  return n > 1 ? 62 - 2 * (32 - __clz((unsigned)(n - 1))) : 62;
 }
 
-constexpr int kSeg = 16;                 // particles per thread on the register path
-constexpr int kRegN = kRT * kSeg;        // largest N on the register path (16384)
-
-// Systematic resampling of a register-resident segment: thread t holds the
-// weights of particles [i0, i0 + cnt).  marks: LDS, n ints.  Writes anc.
-__device__ int resample_seg(const double (&w)[kSeg], int cnt, int i0, int n, uint32_t U,
-                            int* marks, int32_t* __restrict__ anc, double* shd,
-                            unsigned long long* shu, int* shi) {
-  double wmax = -1.0, bad = 0.0;
-#pragma unroll
-  for (int k = 0; k < kSeg; ++k)
-    if (k < cnt) {
-      if (!(w[k] >= 0.0) || isinf(w[k])) bad = 1.0;
-      wmax = fmax(wmax, w[k]);
-    }
-  bad = block_reduce<kMax>(bad, shd);
-  wmax = block_reduce<kMax>(wmax, shd);
-  if (bad != 0.0 || !(wmax > 0.0)) return PHI4_ENONFINITE;
-  const int kb = n > 1 ? 62 - 2 * (32 - __clz((unsigned)(n - 1))) : 62;
+// Systematic resampling of a register-resident segment: this thread holds
+// the weights of particles [i0, i0 + cnt) (contiguous segments in thread
+// order); wmax is the largest weight (> 0, all weights finite and >= 0).
+// marks: LDS, n ints.  Writes anc.
+__device__ void resample_seg(const double (&w)[kSeg], int cnt, int i0, int n, double wmax,
+                             uint32_t U, int* marks, int32_t* __restrict__ anc,
+                             unsigned long long* shu, int* shi) {
+  __shared__ unsigned long long qsh;
+  const int kb = resample_bits(n);
   unsigned long long c[kSeg];
   unsigned long long loc = 0;
 #pragma unroll
@@ -168,9 +112,7 @@ __device__ int resample_seg(const double (&w)[kSeg], int cnt, int i0, int n, uin
   }
   const unsigned long long ex = block_excl_scan_u64(loc, shu);
   for (int i = threadIdx.x; i < n; i += kRT) marks[i] = 0;
-  // Q = C_{n-1}: the inclusive total, broadcast through LDS
-  __shared__ unsigned long long qsh;
-  if (cnt > 0 && i0 + cnt == n) qsh = ex + c[cnt - 1];
+  if (cnt > 0 && i0 + cnt == n) qsh = ex + c[cnt - 1];   // Q = C_{n-1}
   __syncthreads();
   const unsigned long long Q = qsh;
   const unsigned long long uu = (unsigned long long)U;
@@ -195,14 +137,60 @@ __device__ int resample_seg(const double (&w)[kSeg], int cnt, int i0, int n, uin
       run = max(run, marks[i0 + k]);
       anc[i0 + k] = run - 1;
     }
-  return 0;
 }
 
-__device__ Sums ess_sums_lds(const float* Sc, int n, double x, double smin, double* sh) {
+// Same on global memory for n > kRegN (weights w, scratch cdf and marks).
+__device__ void resample_global(const double* __restrict__ w, int n, double wmax, uint32_t U,
+                                unsigned long long* __restrict__ cdf, int32_t* __restrict__ marks,
+                                int32_t* __restrict__ anc, unsigned long long* shu, int* shi) {
+  const int kb = resample_bits(n);
+  const int per = (n + kRT - 1) / kRT;
+  const int i0 = min(n, (int)threadIdx.x * per), i1 = min(n, i0 + per);
+  unsigned long long loc = 0;
+  for (int i = i0; i < i1; ++i) {
+    loc += (unsigned long long)floor(ldexp(w[i] / wmax, kb));
+    cdf[i] = loc;
+  }
+  const unsigned long long ex = block_excl_scan_u64(loc, shu);
+  for (int i = i0; i < i1; ++i) cdf[i] += ex;
+  for (int i = threadIdx.x; i < n; i += kRT) marks[i] = 0;
+  __syncthreads();
+  const unsigned long long Q = cdf[n - 1];
+  const unsigned long long uu = (unsigned long long)U;
+  const unsigned long long off = uu * (Q >> 32) + ((uu * (Q & 0xFFFFFFFFull)) >> 32);
+  for (int j = i0; j < i1; ++j) {
+    const long long lo = count_below(j ? cdf[j - 1] : 0ull, Q, off, n);
+    const long long hi = count_below(cdf[j], Q, off, n);
+    if (hi > lo) marks[lo] = j + 1;
+  }
+  __syncthreads();
+  int mloc = 0;
+  for (int i = i0; i < i1; ++i) mloc = max(mloc, marks[i]);
+  int run = block_excl_scan_max(mloc, shi);
+  for (int i = i0; i < i1; ++i) {
+    run = max(run, marks[i]);
+    anc[i] = run - 1;
+  }
+}
+
+// Resampling weight exp(l - lmax) with l = -dbeta S rounded to float64 on its
+// own (no fused multiply-add), so l <= lmax exactly: every weight is <= 1 and
+// the one at the smallest action is exactly 1.
+__device__ __forceinline__ double tempered_weight(double dbeta, float s, double lmax) {
+#pragma clang fp contract(off)
+  const double l = -dbeta * (double)s;
+  return exp(l - lmax);
+}
+
+// ------------------------------------------------------------ beta solve
+
+// One float64 pass: e_i = exp(-x (S_i - smin)) and the derivatives in x.
+template <class SGet>
+__device__ Sums ess_sums(SGet sget, int n, double x, double smin, double* sh) {
   const double mx = -x * smin;
   double a = 0, b = 0, da = 0, db = 0;
   for (int i = threadIdx.x; i < n; i += kRT) {
-    const double si = (double)Sc[i];
+    const double si = (double)sget(i);
     const double e = exp(-x * si - mx);
     const double sd = si - smin;
     a += e;
@@ -210,14 +198,14 @@ __device__ Sums ess_sums_lds(const float* Sc, int n, double x, double smin, doub
     da -= sd * e;
     db -= 2.0 * sd * e * e;
   }
-  block_sum4(a, b, da, db, sh);
+  block_sum4<kNW>(a, b, da, db, sh);
   return Sums{a, b, da, db};
 }
 
-// Float32 Newton on g(x) = log ESS(x) - log target with the hardware
-// exponential, from x0 to a relative step of 1e-5; only a starting point for
-// the float64 solve, which re-brackets from [0, room].
-__device__ double presolve_f32(const float* Sc, int n, double x0, double room, double ltarget,
+// Float32 Newton with the hardware exponential from x0 to a relative step of
+// 1e-5: only a starting point for the float64 solve, which brackets afresh.
+template <class SGet>
+__device__ double presolve_f32(SGet sget, int n, double x0, double room, double ltarget,
                                double smin, double* sh) {
   double x = x0, lo = 0.0, hi = room;
   const float fsmin = (float)smin;
@@ -225,7 +213,7 @@ __device__ double presolve_f32(const float* Sc, int n, double x0, double room, d
     const float xf = (float)x;
     float a = 0.f, b = 0.f, da = 0.f, db = 0.f;
     for (int i = threadIdx.x; i < n; i += kRT) {
-      const float sd = Sc[i] - fsmin;
+      const float sd = sget(i) - fsmin;
       const float e = __expf(-xf * sd);
       a += e;
       b += e * e;
@@ -233,12 +221,11 @@ __device__ double presolve_f32(const float* Sc, int n, double x0, double room, d
       db -= 2.f * sd * e * e;
     }
     double A = a, B = b, DA = da, DB = db;
-    block_sum4(A, B, DA, DB, sh);
+    block_sum4<kNW>(A, B, DA, DB, sh);
     const double gval = 2.0 * log(A) - log(B) - ltarget;
     const double gder = 2.0 * DA / A - DB / B;
     if (gval >= 0.0) lo = x; else hi = x;
-    const double step = gval / gder;
-    double xn = x - step;
+    double xn = x - gval / gder;
     if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
     const bool fin = fabs(xn - x) <= 1e-5 * x;
     x = xn;
@@ -247,24 +234,25 @@ __device__ double presolve_f32(const float* Sc, int n, double x0, double room, d
   return x;
 }
 
-// Tempering increment: ESS(dbeta) = target by bracketed Newton on
-// g = log ESS - log target; returns the lower end of the final bracket.
-template <class Eval, class Guess>
-__device__ double solve_dbeta(Eval eval, Guess guess, double room, double target, int n,
-                              double ssum, double ssq, Sums& e, int& evals) {
-  e = eval(room);
+// Tempering increment: ESS(dbeta) = target by bracketed float64 Newton on
+// g = log ESS - log target; returns the lower end of the final bracket and
+// the sums at it.
+template <class SGet>
+__device__ double solve_dbeta(SGet sget, int n, double room, double target, double smin,
+                              double ssum, double ssq, double* sh, Sums& e, int& evals) {
+  e = ess_sums(sget, n, room, smin, sh);
   evals = 1;
   if (e.a * e.a / e.b >= target) return room;
   const double ltarget = log(target);
   double lo = 0.0, hi = room;
-  // second-order start: ESS / N ~ 1 / (1 + x^2 Var S), refined by `guess`
+  // second-order start: ESS / N ~ 1 / (1 + x^2 Var S), refined in float32
   const double mean = ssum / n, var = fmax(ssq / n - mean * mean, 0.0);
   double x = var > 0.0 ? sqrt(fmax(n / target - 1.0, 0.0) / var) : 0.5 * room;
   if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
-  x = guess(x, room, ltarget);
+  x = presolve_f32(sget, n, x, room, ltarget, smin, sh);
   if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
   for (int it = 0; it < 200; ++it) {
-    e = eval(x);
+    e = ess_sums(sget, n, x, smin, sh);
     ++evals;
     const double gval = 2.0 * log(e.a) - log(e.b) - ltarget;
     const double gder = 2.0 * e.da / e.a - e.db / e.b;
@@ -277,52 +265,93 @@ __device__ double solve_dbeta(Eval eval, Guess guess, double room, double target
     if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
     x = xn;
   }
-  if (lo > 0.0) {
-    e = eval(lo);
+  if (lo > 0.0 && lo != x) {
+    e = ess_sums(sget, n, lo, smin, sh);
     ++evals;
   }
   return lo;
 }
 
-__global__ __launch_bounds__(kRT) void reweight_kernel(ReweightArgs a) {
-  __shared__ double shd[4 * (kRT / 64)];
-  __shared__ unsigned long long shu[kRT / 64];
-  __shared__ int shi[kRT / 64];
-  __shared__ int marks[kRegN];
-  __shared__ float Sc[kRegN];
+// --------------------------------------------------------------- kernels
+
+// Step-size adaptation of the finished sweep (App. A scaling steered to
+// acc_target): log eps += acc - acc_target, clamped to [eps0/100, 10 eps0].
+__device__ void adapt_eps(SmcState* st) {
+  if (threadIdx.x == 0 && st->prop > 0) {
+    const double abar = (double)st->acc / (double)st->prop;
+    st->last_acc = abar;
+    const double e = st->eps * exp(abar - st->acc_target);
+    st->eps = fmin(fmax(e, st->eps0 / 100.0), 10.0 * st->eps0);
+    st->acc = 0;
+    st->prop = 0;
+  }
+}
+
+__device__ void fail_reweight(const ReweightArgs& a, int code) {
+  if (threadIdx.x == 0) {
+    if (a.st) a.st->err = code;
+    if (a.out) a.out[0] = a.out[1] = a.out[2] = a.out[3] = NAN;
+  }
+}
+
+__device__ void finish_reweight(const ReweightArgs& a, int level, double dbeta, double new_beta,
+                                double dlogz, double ess, int evals) {
+  if (threadIdx.x != 0) return;
+  if (SmcState* st = a.st) {
+    st->logz += dlogz;
+    st->beta = new_beta;
+    st->level = level;
+    st->last_dbeta = dbeta;
+    st->last_ess = ess;
+    st->solve_iters = evals;
+  }
+  if (a.out) {
+    a.out[0] = dbeta;
+    a.out[1] = new_beta;
+    a.out[2] = dlogz;
+    a.out[3] = ess;
+  }
+}
+
+// Returns false if this launch has nothing more to do (run finished or failed).
+__device__ bool reweight_prologue(const ReweightArgs& a, double& beta, double& ess_frac,
+                                  int& level) {
   SmcState* st = a.st;
-  const int n = a.n;
-  double beta, ess_frac;
-  int level = 0;
-  if (st) {
-    if (st->err) return;
-    // step-size adaptation of the finished sweep (App. A scaling steered to
-    // acc_target): log eps += acc - acc_target, clamped to [eps0/100, 10 eps0]
-    if (threadIdx.x == 0 && st->prop > 0) {
-      const double abar = (double)st->acc / (double)st->prop;
-      st->last_acc = abar;
-      const double e = st->eps * exp(abar - st->acc_target);
-      st->eps = fmin(fmax(e, st->eps0 / 100.0), 10.0 * st->eps0);
-      st->acc = 0;
-      st->prop = 0;
-    }
-    if (st->done || st->beta >= 1.0) {
-      // the sweep at beta = 1 is finished: identity ancestors keep the
-      // population in place through the gather that follows
-      for (int i = threadIdx.x; i < n; i += kRT) a.anc[i] = i;
-      __syncthreads();
-      if (threadIdx.x == 0) st->done = 1;
-      return;
-    }
-    beta = st->beta;
-    ess_frac = st->ess_frac;
-    level = st->level + 1;
-  } else {
+  if (!st) {
     beta = a.beta_in;
     ess_frac = a.ess_frac_in;
+    level = 0;
+    return true;
   }
-  // actions in LDS (exact float copies); all loads issued before use
-  double smin = INFINITY, bad = 0.0;
+  if (st->err) return false;
+  adapt_eps(st);
+  if (st->done || st->beta >= 1.0) {
+    // the sweep at beta = 1 is finished: identity ancestors keep the
+    // population in place through the gather that follows
+    for (int i = threadIdx.x; i < a.n; i += kRT) a.anc[i] = i;
+    __syncthreads();
+    if (threadIdx.x == 0) st->done = 1;
+    return false;
+  }
+  beta = st->beta;
+  ess_frac = st->ess_frac;
+  level = st->level + 1;
+  return true;
+}
+
+__global__ __launch_bounds__(kRT) void reweight_kernel(ReweightArgs a) {
+  __shared__ double shd[4 * kNW];
+  __shared__ unsigned long long shu[kNW];
+  __shared__ int shi[kNW];
+  __shared__ int marks[kRegN];
+  __shared__ float Sc[kRegN];
+  double beta, ess_frac;
+  int level;
+  if (!reweight_prologue(a, beta, ess_frac, level)) return;
+  const int n = a.n;
+  // actions into LDS (exact float copies), all loads issued before use; a
+  // non-finite action turns the minimum into -inf (one reduction)
+  double smin = INFINITY;
   {
     float v[kSeg];
 #pragma unroll
@@ -332,194 +361,114 @@ __global__ __launch_bounds__(kRT) void reweight_kernel(ReweightArgs a) {
       const int i = threadIdx.x + k * kRT;
       if (i < n) {
         Sc[i] = v[k];
-        if (!isfinite(v[k])) bad = 1.0;
-        smin = fmin(smin, (double)v[k]);
+        smin = isfinite(v[k]) ? fmin(smin, (double)v[k]) : -INFINITY;
       }
     }
   }
-  bad = block_reduce<kMax>(bad, shd);
-  smin = block_reduce<kMin>(smin, shd);
-  if (bad != 0.0) {
-    if (threadIdx.x == 0) {
-      if (st) st->err = PHI4_ENONFINITE;
-      if (a.out) a.out[0] = a.out[1] = a.out[2] = a.out[3] = NAN;
-    }
-    return;
-  }
+  smin = block_reduce<kMin, kNW>(smin, shd);
+  if (!isfinite(smin)) return fail_reweight(a, PHI4_ENONFINITE);
+  const auto sget = [&](int i) { return Sc[i]; };
   double ssum = 0.0, ssq = 0.0, z0 = 0.0, z1 = 0.0;
   for (int i = threadIdx.x; i < n; i += kRT) {
     const double sd = (double)Sc[i] - smin;
     ssum += sd;
     ssq += sd * sd;
   }
-  block_sum4(ssum, ssq, z0, z1, shd);
+  block_sum4<kNW>(ssum, ssq, z0, z1, shd);
   const double room = 1.0 - beta;
-  const double target = ess_frac * n;
   Sums e;
   int evals = 0;
-  const double dbeta = solve_dbeta(
-      [&](double x) { return ess_sums_lds(Sc, n, x, smin, shd); },
-      [&](double x0, double rm, double lt) { return presolve_f32(Sc, n, x0, rm, lt, smin, shd); },
-      room, target, n, ssum, ssq, e, evals);
-  if (!(dbeta > 0.0)) {
-    if (threadIdx.x == 0) {
-      if (st) st->err = PHI4_ENONFINITE;
-      if (a.out) a.out[0] = a.out[1] = a.out[2] = a.out[3] = NAN;
-    }
-    return;
-  }
+  const double dbeta = solve_dbeta(sget, n, room, ess_frac * n, smin, ssum, ssq, shd, e, evals);
+  if (!(dbeta > 0.0)) return fail_reweight(a, PHI4_ENONFINITE);
   const double new_beta = dbeta == room ? 1.0 : fmin(1.0, beta + dbeta);
   const double dlogz = -dbeta * smin + log(e.a) - log((double)n);
   const double ess = e.a * e.a / e.b;
-  // weights exp(l_i - max l), l_i = -dbeta S_i, for this thread's contiguous segment
+  // weights of this thread's contiguous segment; the largest is exactly 1
   const int per = (n + kRT - 1) / kRT;
   const int i0 = min(n, (int)threadIdx.x * per);
   const int cnt = max(0, min(n, i0 + per) - i0);
+  const double lmax = -dbeta * smin;
   double w[kSeg];
-  const double mx = -dbeta * smin;
 #pragma unroll
-  for (int k = 0; k < kSeg; ++k) {
-    w[k] = k < cnt ? exp(-dbeta * (double)Sc[i0 + k] - mx) : 0.0;
-    if (a.w && k < cnt) a.w[i0 + k] = w[k];
+  for (int k = 0; k < kSeg; ++k) w[k] = k < cnt ? tempered_weight(dbeta, Sc[i0 + k], lmax) : 0.0;
+  if (a.w && !a.st) {
+#pragma unroll
+    for (int k = 0; k < kSeg; ++k)
+      if (k < cnt) a.w[i0 + k] = w[k];
   }
-  int rc = 0;
   if (a.do_resample) {
     const uint32_t U = word0(0u, 0u, counter3((uint32_t)level, PHI4_RESAMPLE), a.seed, a.run);
-    rc = resample_seg(w, cnt, i0, n, U, marks, a.anc, shd, shu, shi);
+    resample_seg(w, cnt, i0, n, 1.0, U, marks, a.anc, shu, shi);
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    if (st) {
-      if (rc) {
-        st->err = rc;
-      } else {
-        st->logz += dlogz;
-        st->beta = new_beta;
-        st->level = level;
-        st->last_dbeta = dbeta;
-        st->last_ess = ess;
-        st->solve_iters = evals;
-      }
-    }
-    if (a.out) {
-      a.out[0] = dbeta;
-      a.out[1] = new_beta;
-      a.out[2] = dlogz;
-      a.out[3] = ess;
-    }
-  }
+  finish_reweight(a, level, dbeta, new_beta, dlogz, ess, evals);
 }
 
 // Large-N variant: actions and weights stay in global memory.
 __global__ __launch_bounds__(kRT) void reweight_global_kernel(ReweightArgs a) {
-  __shared__ double shd[4 * (kRT / 64)];
-  __shared__ unsigned long long shu[kRT / 64];
-  __shared__ int shi[kRT / 64];
-  SmcState* st = a.st;
-  const int n = a.n;
+  __shared__ double shd[4 * kNW];
+  __shared__ unsigned long long shu[kNW];
+  __shared__ int shi[kNW];
   double beta, ess_frac;
-  int level = 0;
-  if (st) {
-    if (st->err) return;
-    if (threadIdx.x == 0 && st->prop > 0) {
-      const double abar = (double)st->acc / (double)st->prop;
-      st->last_acc = abar;
-      const double e = st->eps * exp(abar - st->acc_target);
-      st->eps = fmin(fmax(e, st->eps0 / 100.0), 10.0 * st->eps0);
-      st->acc = 0;
-      st->prop = 0;
-    }
-    if (st->done || st->beta >= 1.0) {
-      for (int i = threadIdx.x; i < n; i += kRT) a.anc[i] = i;
-      __syncthreads();
-      if (threadIdx.x == 0) st->done = 1;
-      return;
-    }
-    beta = st->beta;
-    ess_frac = st->ess_frac;
-    level = st->level + 1;
-  } else {
-    beta = a.beta_in;
-    ess_frac = a.ess_frac_in;
-  }
-  double smin = INFINITY, bad = 0.0;
+  int level;
+  if (!reweight_prologue(a, beta, ess_frac, level)) return;
+  const int n = a.n;
+  double smin = INFINITY;
   for (int i = threadIdx.x; i < n; i += kRT) {
-    const double si = (double)a.S[i];
-    if (!isfinite(si)) bad = 1.0;
-    smin = fmin(smin, si);
+    const float v = a.S[i];
+    smin = isfinite(v) ? fmin(smin, (double)v) : -INFINITY;
   }
-  bad = block_reduce<kMax>(bad, shd);
-  smin = block_reduce<kMin>(smin, shd);
-  if (bad != 0.0) {
-    if (threadIdx.x == 0) {
-      if (st) st->err = PHI4_ENONFINITE;
-      if (a.out) a.out[0] = a.out[1] = a.out[2] = a.out[3] = NAN;
-    }
-    return;
-  }
+  smin = block_reduce<kMin, kNW>(smin, shd);
+  if (!isfinite(smin)) return fail_reweight(a, PHI4_ENONFINITE);
+  const float* S = a.S;
+  const auto sget = [&](int i) { return S[i]; };
   double ssum = 0.0, ssq = 0.0, z0 = 0.0, z1 = 0.0;
   for (int i = threadIdx.x; i < n; i += kRT) {
-    const double sd = (double)a.S[i] - smin;
+    const double sd = (double)S[i] - smin;
     ssum += sd;
     ssq += sd * sd;
   }
-  block_sum4(ssum, ssq, z0, z1, shd);
+  block_sum4<kNW>(ssum, ssq, z0, z1, shd);
   const double room = 1.0 - beta;
   Sums e;
   int evals = 0;
-  const double dbeta = solve_dbeta(
-      [&](double x) { return ess_sums(a.S, n, x, smin, shd); },
-      [](double x0, double, double) { return x0; }, room, ess_frac * n, n, ssum, ssq, e, evals);
-  if (!(dbeta > 0.0)) {
-    if (threadIdx.x == 0) {
-      if (st) st->err = PHI4_ENONFINITE;
-      if (a.out) a.out[0] = a.out[1] = a.out[2] = a.out[3] = NAN;
-    }
-    return;
-  }
+  const double dbeta = solve_dbeta(sget, n, room, ess_frac * n, smin, ssum, ssq, shd, e, evals);
+  if (!(dbeta > 0.0)) return fail_reweight(a, PHI4_ENONFINITE);
   const double new_beta = dbeta == room ? 1.0 : fmin(1.0, beta + dbeta);
   const double dlogz = -dbeta * smin + log(e.a) - log((double)n);
   const double ess = e.a * e.a / e.b;
-  if (a.w) {
-    const double mx = -dbeta * smin;
-    for (int i = threadIdx.x; i < n; i += kRT) a.w[i] = exp(-dbeta * (double)a.S[i] - mx);
-  }
+  const double lmax = -dbeta * smin;
+  if (a.w)
+    for (int i = threadIdx.x; i < n; i += kRT) a.w[i] = tempered_weight(dbeta, S[i], lmax);
   __syncthreads();
-  int rc = 0;
   if (a.do_resample) {
     const uint32_t U = word0(0u, 0u, counter3((uint32_t)level, PHI4_RESAMPLE), a.seed, a.run);
-    rc = resample_block(a.w, n, U, a.cdf, a.marks, a.anc, shd, shu, shi);
+    resample_global(a.w, n, 1.0, U, a.cdf, a.marks, a.anc, shu, shi);
   }
-  if (threadIdx.x == 0) {
-    if (st) {
-      if (rc) {
-        st->err = rc;
-      } else {
-        st->logz += dlogz;
-        st->beta = new_beta;
-        st->level = level;
-        st->last_dbeta = dbeta;
-        st->last_ess = ess;
-        st->solve_iters = evals;
-      }
-    }
-    if (a.out) {
-      a.out[0] = dbeta;
-      a.out[1] = new_beta;
-      a.out[2] = dlogz;
-      a.out[3] = ess;
-    }
-  }
+  __syncthreads();
+  finish_reweight(a, level, dbeta, new_beta, dlogz, ess, evals);
 }
 
+// Stand-alone resampling of caller weights: checks them (finite, >= 0,
+// max > 0) and resamples with the largest weight as the scale.
 __global__ __launch_bounds__(kRT) void resample_kernel(const double* w, int n, uint32_t U,
                                                        unsigned long long* cdf, int32_t* marks,
                                                        int32_t* anc, int32_t* status) {
-  __shared__ double shd[4 * (kRT / 64)];
-  __shared__ unsigned long long shu[kRT / 64];
-  __shared__ int shi[kRT / 64];
+  __shared__ double shd[kNW];
+  __shared__ unsigned long long shu[kNW];
+  __shared__ int shi[kNW];
   __shared__ int mlds[kRegN];
-  int rc;
+  // one max-reduction decides validity: an invalid weight maps to +inf
+  double wmax = -1.0;
+  for (int i = threadIdx.x; i < n; i += kRT) {
+    const double x = w[i];
+    wmax = (x >= 0.0 && !isinf(x)) ? fmax(wmax, x) : INFINITY;
+  }
+  wmax = block_reduce<kMax, kNW>(wmax, shd);
+  if (isinf(wmax) || !(wmax > 0.0)) {
+    if (threadIdx.x == 0 && status) *status = PHI4_ENONFINITE;
+    return;
+  }
   if (n <= kRegN) {
     const int per = (n + kRT - 1) / kRT;
     const int i0 = min(n, (int)threadIdx.x * per);
@@ -530,11 +479,11 @@ __global__ __launch_bounds__(kRT) void resample_kernel(const double* w, int n, u
       const double v = w[min(i0 + k, n - 1)];   // valid address, masked
       wv[k] = k < cnt ? v : 0.0;
     }
-    rc = resample_seg(wv, cnt, i0, n, U, mlds, anc, shd, shu, shi);
+    resample_seg(wv, cnt, i0, n, wmax, U, mlds, anc, shu, shi);
   } else {
-    rc = resample_block(w, n, U, cdf, marks, anc, shd, shu, shi);
+    resample_global(w, n, wmax, U, cdf, marks, anc, shu, shi);
   }
-  if (threadIdx.x == 0 && status) *status = rc;
+  if (threadIdx.x == 0 && status) *status = 0;
 }
 
 __global__ void smc_state_init_kernel(SmcState* st, double eps0, double acc_target,
@@ -565,13 +514,11 @@ __global__ void ns_state_init_kernel(NsState* st, double eps0, double acc_target
   *st = s;
 }
 
-__global__ __launch_bounds__(kRT) void mean_abs_kernel(const float* absM, int n, double* out,
-                                                       const int32_t* done) {
-  __shared__ double shd[kRT / 64];
-  (void)done;
+__global__ __launch_bounds__(kRT) void mean_abs_kernel(const float* absM, int n, double* out) {
+  __shared__ double shd[kNW];
   double s = 0.0;
   for (int i = threadIdx.x; i < n; i += kRT) s += (double)absM[i];
-  s = block_reduce<kSum>(s, shd);
+  s = block_reduce<kSum, kNW>(s, shd);
   if (threadIdx.x == 0) *out = s / n;
 }
 
@@ -600,8 +547,9 @@ void launch_ns_state_init(NsState* st, double eps0, double acc_target, hipStream
 }
 
 void launch_mean_abs(const float* absM, int n, double* out, const int32_t* done, hipStream_t s) {
+  (void)done;
   if (n <= 0) return;
-  mean_abs_kernel<<<1, kRT, 0, s>>>(absM, n, out, done);
+  mean_abs_kernel<<<1, kRT, 0, s>>>(absM, n, out);
 }
 
 }  // namespace phi4
