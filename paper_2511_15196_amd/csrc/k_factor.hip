@@ -366,19 +366,17 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
   double* sig = a.sigma_out;
   const double* src = a.sigma_in ? a.sigma_in : sig;
   // stage the matrix (clamped valid addresses, all loads of a batch in flight)
-  constexpr int kPer = D * D / 64;                // entries per lane
-  constexpr int kB = kPer < 16 ? kPer : 16;       // loads in flight
+  constexpr int kPer = D * D / 64;                // entries per lane, all in flight
+  {
+    double x[kPer];
 #pragma unroll
-  for (int b = 0; b < kPer; b += kB) {
-    double x[kB];
-#pragma unroll
-    for (int q = 0; q < kB; ++q) {
-      const int e = (b + q) * 64 + i, r = e / D, cc = e % D;
+    for (int q = 0; q < kPer; ++q) {
+      const int e = q * 64 + i, r = e / D, cc = e % D;
       x[q] = src[(size_t)min(r, d - 1) * d + min(cc, d - 1)];
     }
 #pragma unroll
-    for (int q = 0; q < kB; ++q) {
-      const int e = (b + q) * 64 + i, r = e / D, cc = e % D;
+    for (int q = 0; q < kPer; ++q) {
+      const int e = q * 64 + i, r = e / D, cc = e % D;
       const bool in = r < d && cc < d;
       M[r][cc] = in ? x[q] : (r == cc ? 1.0 : 0.0);
       if (a.sigma_in && in) sig[(size_t)r * d + cc] = x[q];
@@ -413,16 +411,20 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
   const double sq = sqrt(pown);
   col[0][i] = 1.0 / sq;
   __syncthreads();
-  if (!rv) return;
   const double eps = a.Bt ? *a.eps_ptr : 0.0;
 #pragma unroll
-  for (int j = 0; j < D; ++j)
-    if (j < d) {
-      const double l = j < i ? v[j] * col[0][j] : (j == i ? sq : 0.0);
-      a.A[(size_t)i * d + j] = l;
-      // Bt[k][c] = eps L[c][k]: this entry is L[i][j] -> Bt[j][i]
-      if (a.Bt) a.Bt[(size_t)j * a.ldb + i] = (float)(eps * l);
-    }
+  for (int j = 0; j < D; ++j) {
+    const double l = j < i ? v[j] * col[0][j] : (j == i ? sq : 0.0);
+    if (i < D) M[i][j] = l;
+    // Bt[k][c] = eps L[c][k]: this entry is L[i][j] -> Bt[j][i] (coalesced over lanes)
+    if (a.Bt && rv && j < d) a.Bt[(size_t)j * a.ldb + i] = (float)(eps * l);
+  }
+  __syncthreads();
+  // the float64 factor row by row from LDS (coalesced)
+  if (a.A && rv) {
+#pragma unroll 8
+    for (int r = 0; r < d; ++r) a.A[(size_t)r * d + i] = M[r][i];
+  }
   if (i == 0 && a.tau_out) *a.tau_out = tau;
 }
 
