@@ -107,8 +107,11 @@ size_t smc_workspace_bytes(const phi4_smc_config* cfg);
  * log Z = 0, eps = eps0.  phi, S and workspace (>= smc_workspace_bytes,
  * 256-byte aligned) stay owned by the caller; *handle receives host
  * metadata only.  After smc_init, smc_mutate and smc_run the current
- * particles are in phi / S; after smc_reweight_resample the resampled
- * particles sit in the workspace until the next smc_mutate moves them. */
+ * particles are in phi / S; smc_reweight_resample leaves them there and
+ * keeps the resampling ancestors in the workspace, and the next smc_mutate
+ * starts particle i from ancestor anc[i] (inside smc_run the particles
+ * alternate between phi / S and a workspace copy and are back in phi / S
+ * when it returns). */
 int smc_init(const phi4_smc_config* cfg, float* phi, float* S, void* workspace,
              size_t workspace_bytes, void* stream, void** handle);
 

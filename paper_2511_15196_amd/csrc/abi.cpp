@@ -124,7 +124,8 @@ struct Handle {
   // SMC
   phi4_smc_config smc;
   SmcBufs sb;
-  int cur;  // 0: particles in phi/S, 1: in the workspace copy
+  int cur;          // 0: particles in phi/S, 1: in the workspace copy
+  bool anc_pending; // resampling ancestors computed, not yet applied
   CovPlan plan;
   // NS
   phi4_ns_config ns;
@@ -183,14 +184,39 @@ int state_error(int err) {
   return fail(err, "device error");
 }
 
+float* cur_phi(Handle* h) { return h->cur ? h->sb.alt_phi : h->phi; }
+float* cur_S(Handle* h) { return h->cur ? h->sb.alt_S : h->S; }
+float* other_phi(Handle* h) { return h->cur ? h->phi : h->sb.alt_phi; }
+float* other_S(Handle* h) { return h->cur ? h->S : h->sb.alt_S; }
+
+// Applies pending resampling ancestors by a gather into the other buffer.
+void materialize(Handle* h) {
+  if (!h->anc_pending) return;
+  launch_gather(cur_phi(h), cur_S(h), h->sb.anc, h->n, h->d, other_phi(h), other_S(h), nullptr,
+                h->stream);
+  h->cur ^= 1;
+  h->anc_pending = false;
+}
+
+// Moves the particles back to the caller's phi / S if they sit in the workspace.
+int settle(Handle* h) {
+  if (h->anc_pending) materialize(h);
+  if (!h->cur) return PHI4_OK;
+  HIP_TRY(hipMemcpyAsync(h->phi, h->sb.alt_phi, sizeof(float) * (size_t)h->n * h->d,
+                         hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(hipMemcpyAsync(h->S, h->sb.alt_S, sizeof(float) * (size_t)h->n,
+                         hipMemcpyDeviceToDevice, h->stream));
+  h->cur = 0;
+  return PHI4_OK;
+}
+
+// Reweighting, resampling ancestors, and the covariance factor of the
+// resampled population (read through the ancestors; nothing is copied).
 int enqueue_reweight(Handle* h) {
   SmcBufs& b = h->sb;
-  float* curS = h->cur ? b.alt_S : h->S;
-  float* curP = h->cur ? b.alt_phi : h->phi;
-  float* othS = h->cur ? h->S : b.alt_S;
-  float* othP = h->cur ? h->phi : b.alt_phi;
+  materialize(h);
   ReweightArgs ra = {};
-  ra.S = curS;
+  ra.S = cur_S(h);
   ra.n = h->n;
   ra.st = b.st;
   ra.w = b.w;
@@ -201,10 +227,8 @@ int enqueue_reweight(Handle* h) {
   ra.marks = b.marks;
   ra.anc = b.anc;
   launch_reweight(ra, h->stream);
-  launch_gather(curP, curS, b.anc, h->n, h->d, othP, othS, nullptr, h->stream);
-  h->cur ^= 1;
-  float* newP = h->cur ? b.alt_phi : h->phi;
-  launch_cov_partials(newP, nullptr, h->plan, b.part, &b.st->done, h->stream);
+  h->anc_pending = true;
+  launch_cov_partials(cur_phi(h), b.anc, h->plan, b.part, &b.st->done, h->stream);
   FactorArgs fa = {};
   fa.part = b.part;
   fa.plan = h->plan;
@@ -220,11 +244,14 @@ int enqueue_reweight(Handle* h) {
   return hip_check("smc_reweight_resample");
 }
 
+// One sweep from the current particles (through pending ancestors) into the
+// other buffer.
 int enqueue_mutate(Handle* h) {
   SmcBufs& b = h->sb;
   MutateArgs m = {};
-  m.src = h->cur ? b.alt_phi : h->phi;
-  m.dst = h->phi;
+  m.src = cur_phi(h);
+  m.src_rows = h->anc_pending ? b.anc : nullptr;
+  m.dst = other_phi(h);
   m.rows = nullptr;
   m.n = h->n;
   m.L = h->L;
@@ -242,7 +269,7 @@ int enqueue_mutate(Handle* h) {
   m.n_steps = h->n_steps;
   m.zsign = 1.0f;
   m.done_ptr = &b.st->done;
-  m.S = h->S;
+  m.S = other_S(h);
   m.absM = b.absM;
   m.acc_count = &b.st->acc;
   m.prop_count = &b.st->prop;
@@ -252,7 +279,8 @@ int enqueue_mutate(Handle* h) {
     rc = launch_mutate(m, h->precision, h->stream);
   }
   if (rc) return fail(rc, "smc_mutate: unsupported shape");
-  h->cur = 0;
+  h->cur ^= 1;
+  h->anc_pending = false;
   return hip_check("smc_mutate");
 }
 
@@ -432,6 +460,7 @@ int smc_restart(void* handle, uint32_t seed, uint32_t run) {
   h->smc.seed = seed;
   h->smc.run = run;
   h->cur = 0;
+  h->anc_pending = false;
   launch_smc_state_init(h->sb.st, default_eps0(h->d, h->smc.eps0), h->smc.acc_target,
                         h->smc.ess_frac, h->stream);
   launch_init_fields(h->phi, h->S, h->sb.absM, h->n, h->L, h->m2, h->lam, 1.0f, seed, run,
@@ -457,6 +486,7 @@ int smc_mutate(void* handle, double* acc_host) {
   Handle* h = as_handle(handle, 0);
   if (!h) return fail(PHI4_EINVAL, "smc_mutate: not an SMC handle");
   int rc = enqueue_mutate(h);
+  if (!rc) rc = settle(h);
   if (rc) return rc;
   if (!acc_host) return PHI4_OK;
   SmcState* s = static_cast<SmcState*>(h->pinned);
@@ -491,6 +521,8 @@ int smc_run(void* handle, int32_t max_levels, int32_t* levels_host) {
       if (s.beta >= 1.0) finished = true;
     }
   }
+  rc = settle(h);
+  if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(h->stream));
   // the level enqueued after the final sweep did no work: drop its timing
   if (finished && h->timing && h->tused > 0) --h->tused;
@@ -639,8 +671,8 @@ int phi4_observables(void* handle, double* out) {
   if (!h || !out) return fail(PHI4_EINVAL, "phi4_observables: NULL argument");
   if (h->kind == 0) {
     SmcBufs& b = h->sb;
-    const float* curP = h->cur ? b.alt_phi : h->phi;
-    launch_action(curP, h->n, h->L, h->m2, h->lam, b.obs_S, b.obs_absM, h->stream);
+    materialize(h);
+    launch_action(cur_phi(h), h->n, h->L, h->m2, h->lam, b.obs_S, b.obs_absM, h->stream);
     launch_mean_abs(b.obs_absM, h->n, &b.st->mean_abs_m, nullptr, h->stream);
     int rc = hip_check("phi4_observables");
     if (rc) return rc;

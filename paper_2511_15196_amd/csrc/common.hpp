@@ -244,8 +244,10 @@ struct NsState {
 
 struct MutateArgs {
   const float* src;        // input rows
-  float* dst;              // output rows (may equal src)
+  float* dst;              // output rows (may equal src unless src_rows is set)
   const int32_t* rows;     // physical row of tile slot i (NULL: i)
+  const int32_t* src_rows; // source row of slot i's initial field (NULL: its own row);
+                           // the resampling ancestors, dst != src
   int32_t n;               // rows processed
   int32_t L, d;
   float m2, lam;
@@ -262,7 +264,8 @@ struct MutateArgs {
   const int32_t* level_ptr;
   int32_t step0, n_steps;
   float zsign;
-  const int32_t* done_ptr; // skip all work if *done_ptr != 0
+  const int32_t* done_ptr; // if *done_ptr != 0: no Metropolis steps; rows are still
+                           // copied (with their action) when dst != src
   float* S;                // out: action of final rows (indexed by row)
   float* absM;             // out (optional)
   unsigned long long* acc_count;

@@ -428,6 +428,207 @@ __global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
   if (i == 0 && a.tau_out) *a.tau_out = tau;
 }
 
+// ------------------------------------------------ fused small-d kernel
+
+constexpr int kCF = 512;   // threads of the fused covariance + factor kernel
+
+// Orders LDS traffic among the lanes of one wave (its LDS operations are
+// processed in order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Step K of a 16-column panel sweep by one wave: lane i holds D[i][c0 + q]
+// in v[q]; column c0 + K sits in col[K & 1]; rp = 1 / D[c0+K][c0+K].
+template <int K>
+__device__ __forceinline__ void panel_step(double (&v)[16], double (*col)[64], int i, int c0,
+                                           double& rp, double& pown, bool& bad) {
+  const double* ck = col[K & 1];
+  const double f = v[K] * rp;
+  if constexpr (K + 1 < 16) {
+    v[K + 1] = fma(-f, ck[c0 + K + 1], v[K + 1]);
+    col[(K + 1) & 1][i] = v[K + 1];            // publish column c0 + K + 1 early
+    __builtin_amdgcn_sched_barrier(0);
+    pown = i == c0 + K + 1 ? v[K + 1] : pown;  // its pivot's lane keeps it
+    const double pn = readlane64(v[K + 1], c0 + K + 1);
+    bad |= !(pn > 0.0) | isinf(pn);
+    rp = recip_f64(pn);
+  }
+#pragma unroll
+  for (int j = K + 2; j < 16; ++j) v[j] = fma(-f, ck[c0 + j], v[j]);
+  wave_sync();
+}
+
+template <int... K>
+__device__ __forceinline__ void panel_sweep(double (&v)[16], double (*col)[64], int i, int c0,
+                                            double& rp, double& pown, bool& bad,
+                                            std::integer_sequence<int, K...>) {
+  (panel_step<K>(v, col, i, c0, rp, pown, bad), ...);
+}
+
+// Covariance from the partials and its jittered Cholesky factor in one
+// workgroup, for d <= D (D = 16, 32, 64; the matrix is padded to D x D with
+// the identity).  The chunk partials are summed in float64 in chunk order,
+// Sigma = (M2 - m1_i m1_j / N) / (N - 1), into LDS (and sigma_out).  The
+// factor is right-looking in 16-column panels: wave 0 sweeps a panel in
+// registers (lane = row, outer-product steps, pivots read from their lane),
+// then every wave applies the rank-16 update to the trailing lower triangle.
+template <int D>
+__global__ __launch_bounds__(kCF) void cov_factor_kernel(FactorArgs a) {
+  if (a.done && *a.done) return;
+  __shared__ double M[D][D + 1];
+  __shared__ double Ms[D][D + 1];   // the covariance again, for retries
+  __shared__ double col[2][64];
+  __shared__ double m1s[64];
+  __shared__ double rs[64];
+  __shared__ int flag;
+  const CovPlan& p = a.plan;
+  const int d = p.d, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const double eps = a.Bt ? *a.eps_ptr : 0.0;      // issued early, used at the end
+  double* sig = a.sigma_out;
+  constexpr int NBD = D / 16, BLKS = NBD * (NBD + 1) / 2;
+  constexpr int EPT = (BLKS * 256 + kCF - 1) / kCF;   // padded entries per thread
+
+  // ---- covariance into M
+  auto load_padded = [&](const double* src) {
+    for (int e = tid; e < D * D; e += kCF) {
+      const int r = e / D, c = e % D;
+      const double x = src[(size_t)min(r, d - 1) * d + min(c, d - 1)];
+      M[r][c] = (r < d && c < d) ? x : (r == c ? 1.0 : 0.0);
+    }
+  };
+  if (a.sigma_in) {
+    load_padded(a.sigma_in);
+    __syncthreads();
+    for (int e = tid; e < d * d; e += kCF) sig[e] = M[e / d][e % d];
+  } else {
+    const float* part1 = a.part + (size_t)p.chunks * p.blocks * 256;
+    if (tid < 64) {
+      float x[kMaxChunks];
+#pragma unroll
+      for (int c = 0; c < kMaxChunks; ++c)
+        x[c] = part1[(size_t)min(c, p.chunks - 1) * p.nb * 16 + min(tid, d - 1)];
+      double m = 0.0;
+#pragma unroll
+      for (int c = 0; c < kMaxChunks; ++c) m += c < p.chunks ? (double)x[c] : 0.0;
+      m1s[tid] = m;
+    }
+    // this thread's entries: all chunk loads in flight
+    float x[EPT][kMaxChunks];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = min(tid + q * kCF, BLKS * 256 - 1);
+      const int blk = min(e >> 8, p.blocks - 1);
+#pragma unroll
+      for (int c = 0; c < kMaxChunks; ++c)
+        x[q][c] = a.part[((size_t)min(c, p.chunks - 1) * p.blocks + blk) * 256 + (e & 255)];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = tid + q * kCF;
+      if (e >= BLKS * 256) break;
+      const int blk = e >> 8, r = (e >> 4) & 15, cc = e & 15;
+      int bi = 0;
+      while ((bi + 1) * (bi + 2) / 2 <= blk) ++bi;
+      const int bj = blk - bi * (bi + 1) / 2;
+      const int i = 16 * bi + r, j = 16 * bj + cc;
+      if (j > i) continue;                      // its mirror entry writes both
+      double v;
+      if (i < d && j < d) {
+        double m2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < kMaxChunks; ++c) m2 += c < p.chunks ? (double)x[q][c] : 0.0;
+        v = (m2 - m1s[i] * m1s[j] / p.n) / (p.n - 1);
+        sig[(size_t)i * d + j] = v;
+        sig[(size_t)j * d + i] = v;
+      } else {
+        v = i == j ? 1.0 : 0.0;
+      }
+      M[i][j] = v;
+      M[j][i] = v;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < D * D; e += kCF) Ms[e / D][e % D] = M[e / D][e % D];
+
+  // ---- jitter: tau = 1e-10 tr / d, x100 per failed attempt (five retries)
+  const double tr = wave_red<kSum>(lane < d ? M[min(lane, D - 1)][min(lane, D - 1)] : 0.0);
+  double tau = 1e-10 * tr / d;
+  bool ok = false;
+  for (int attempt = 0; attempt < 6 && !ok; ++attempt) {
+    if (attempt) {
+      tau *= 100.0;
+      for (int e = tid; e < D * D; e += kCF) M[e / D][e % D] = Ms[e / D][e % D];
+      __syncthreads();
+    }
+    if (tid < d) M[tid][tid] += tau;
+    if (tid == 0) flag = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < D; c0 += 16) {
+      if (wv == 0) {
+        const int ir = min(lane, D - 1);        // lanes beyond D mirror row D - 1, unused
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = M[ir][c0 + q];
+        col[0][lane] = v[0];
+        wave_sync();
+        const double p0 = readlane64(v[0], c0);
+        bool bad = !(p0 > 0.0) | isinf(p0);
+        double rp = recip_f64(p0);
+        double pown = lane == c0 ? v[0] : 1.0;
+        panel_sweep(v, col, lane, c0, rp, pown, bad, std::make_integer_sequence<int, 16>{});
+        // L[i][c0+q] = D[i][c0+q] / sqrt(pivot q) below the diagonal
+        const double sq = sqrt(pown);
+        if (lane >= c0 && lane < c0 + 16) rs[lane] = 1.0 / sq;
+        wave_sync();
+        if (lane >= c0 && lane < D) {
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            const int j = c0 + q;
+            if (lane > j) M[lane][j] = v[q] * rs[j];
+            else if (lane == j) M[lane][j] = sq;
+          }
+        }
+        if (bad && lane == 0) flag = 1;
+      }
+      __syncthreads();
+      if (flag) break;
+      // rank-16 update of the trailing lower triangle
+      const int t0 = c0 + 16, T = D - t0;
+      for (int e = tid; e < T * T; e += kCF) {
+        const int ii = e / T, jj = e - ii * T;
+        if (jj > ii) continue;
+        const int i = t0 + ii, j = t0 + jj;
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc = fma(M[i][c0 + q], M[j][c0 + q], acc);
+        M[i][j] -= acc;
+      }
+      __syncthreads();
+    }
+    ok = flag == 0;
+    __syncthreads();
+  }
+  if (!ok) {
+    if (tid == 0 && a.err_out) *a.err_out = PHI4_ECHOL;
+    return;
+  }
+  // ---- outputs: the float64 factor (zero above the diagonal) and
+  // Bt[k][c] = eps L[c][k] in float32, both coalesced
+  for (int e = tid; e < d * d; e += kCF) {
+    const int i = e / d, j = e - i * d;
+    if (a.A) a.A[e] = j <= i ? M[i][j] : 0.0;
+    if (a.Bt) {
+      const int k = i, c = j;   // Bt row k, column c
+      a.Bt[(size_t)k * a.ldb + c] = c >= k ? (float)(eps * M[c][k]) : 0.f;
+    }
+  }
+  if (tid == 0 && a.tau_out) *a.tau_out = tau;
+}
+
 }  // namespace
 
 CovPlan cov_plan(int n, int d) {
@@ -461,16 +662,23 @@ void launch_cov_partials(const float* phi, const int32_t* rows, const CovPlan& p
 }
 
 void launch_factor(const FactorArgs& a, hipStream_t s) {
+  const int d = a.plan.d;
+  if (!a.cov_only && d <= kSmallD && a.plan.chunks <= kMaxChunks) {
+    // covariance reduction and factor in one workgroup
+    if (d <= 16)
+      cov_factor_kernel<16><<<1, kCF, 0, s>>>(a);
+    else if (d <= 32)
+      cov_factor_kernel<32><<<1, kCF, 0, s>>>(a);
+    else
+      cov_factor_kernel<kSmallD><<<1, kCF, 0, s>>>(a);
+    return;
+  }
   if (!a.sigma_in) {
     const int entries = a.plan.blocks * 256;
     cov_reduce_kernel<<<(entries + 255) / 256, 256, 0, s>>>(a.part, a.plan, a.sigma_out, a.done);
   }
   if (a.cov_only) return;
-  if (a.plan.d <= 16)
-    factor_wave_kernel<16><<<1, 64, 0, s>>>(a);
-  else if (a.plan.d <= 32)
-    factor_wave_kernel<32><<<1, 64, 0, s>>>(a);
-  else if (a.plan.d <= kSmallD)
+  if (d <= kSmallD)
     factor_wave_kernel<kSmallD><<<1, 64, 0, s>>>(a);
   else
     factor_kernel<<<1, kFT, 0, s>>>(a);

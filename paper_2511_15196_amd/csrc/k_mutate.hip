@@ -67,11 +67,12 @@ __device__ __forceinline__ float row16_sum(float v) {
   return v;
 }
 
-template <int DP_, int W_, int PREC_>
+template <int DP_, int W_, int PREC_, int KIND_>
 struct Cfg {
   static constexpr int DP = DP_;
   static constexpr int W = W_;
   static constexpr int PREC = PREC_;
+  static constexpr bool CONSTRAINED = KIND_ == 1;   // likelihood-constrained (else tempered)
   static constexpr bool F32 = PREC_ == PHI4_FP32;
   static constexpr int NB = DP / 16;
   static constexpr int NBW = NB / W;
@@ -96,7 +97,9 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
   using ZT = typename std::conditional<F32, float, unsigned short>::type;
   using FragT = typename std::conditional<F32, f32x4, u16x8>::type;
 
-  if (a.done_ptr && *a.done_ptr) return;
+  // a finished run does no steps; an out-of-place call still moves its rows
+  const bool finished = a.done_ptr && *a.done_ptr;
+  if (finished && a.dst == a.src) return;
 
   __shared__ __align__(16) ZT zs[2][16 * ZS];     // normals of steps s (cur) and s+1
   __shared__ __align__(16) float xo[16 * XS];
@@ -115,11 +118,12 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
   const int level = a.level_ptr ? *a.level_ptr : a.level;
   const uint32_t c3p = counter3((uint32_t)level, PHI4_PROPOSE);
   const uint32_t c3a = counter3((uint32_t)level, PHI4_ACCEPT);
-  const bool constrained = a.kind == 1;
-  const int nsteps = a.n_steps;
+  constexpr bool constrained = C::CONSTRAINED;
+  const int nsteps = finished ? 0 : a.n_steps;
 
-  // rows of this lane's output particles (tile slots 4g + jj)
-  int orow[4];
+  // rows of this lane's output particles (tile slots 4g + jj) and of the
+  // fields they start from
+  int orow[4], irow[4];
   bool oval[4];
 #pragma unroll
   for (int jj = 0; jj < 4; ++jj) {
@@ -128,6 +132,8 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
     const int ic = min(i, n - 1);              // valid index, masked below
     const int r = a.rows ? a.rows[ic] : ic;
     orow[jj] = oval[jj] ? r : 0;
+    const int ri = a.src_rows ? a.src_rows[ic] : r;
+    irow[jj] = oval[jj] ? ri : 0;
   }
 
   // owned column blocks, columns and periodic neighbours
@@ -182,7 +188,7 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj)
     {
-      const float v = a.src[(size_t)orow[jj] * d + min(col[j], d - 1)];
+      const float v = a.src[(size_t)irow[jj] * d + min(col[j], d - 1)];
       ph[j][jj] = (oval[jj] && cval[j]) ? v : 0.f;
     }
 
@@ -260,23 +266,21 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
   for (int s = 0; s < nsteps; ++s) {
     const int cb = s & 1;
     // ---- proposal phi' = phi + Bt^T z for the owned column blocks (MFMA)
+    f32x4 acc[NBW], accn[NBW], acc2[NBW], acc3[NBW];  // float32: four independent chains
 #pragma unroll
     for (int j = 0; j < NBW; ++j) {
       const int nb = nbs[j];
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};    // float32: four independent chains
-      f32x4 accn = {0.f, 0.f, 0.f, 0.f};
-      f32x4 acc2 = {0.f, 0.f, 0.f, 0.f};
-      f32x4 acc3 = {0.f, 0.f, 0.f, 0.f};
+      acc[j] = accn[j] = acc2[j] = acc3[j] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int t = 0; t < C::TB(j); ++t) {
         if constexpr (F32) {
           if (t <= nb) {
             const float4 zq = *reinterpret_cast<const float4*>(&zs[cb][p * ZS + 16 * t + 4 * g]);
             const f32x4 b = bfr[C::OFF(j) + t];
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(zq.x, b[0], acc, 0, 0, 0);
-            accn = __builtin_amdgcn_mfma_f32_16x16x4f32(zq.y, b[1], accn, 0, 0, 0);
-            acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(zq.z, b[2], acc2, 0, 0, 0);
-            acc3 = __builtin_amdgcn_mfma_f32_16x16x4f32(zq.w, b[3], acc3, 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(zq.x, b[0], acc[j], 0, 0, 0);
+            accn[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(zq.y, b[1], accn[j], 0, 0, 0);
+            acc2[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(zq.z, b[2], acc2[j], 0, 0, 0);
+            acc3[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(zq.w, b[3], acc3[j], 0, 0, 0);
           }
         } else {
           if (2 * t <= nb) {
@@ -284,30 +288,40 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
             const u16x8 zn = za ^ (unsigned short)0x8000u;   // -z, exact
             const FragT b = bfr[C::OFF(j) + t];
             if constexpr (C::PREC == PHI4_BF16) {
-              acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, za),
-                                                            __builtin_bit_cast(bf16x8, b), acc,
-                                                            0, 0, 0);
-              accn = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, zn),
-                                                             __builtin_bit_cast(bf16x8, b), accn,
-                                                             0, 0, 0);
+              acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, za),
+                                                               __builtin_bit_cast(bf16x8, b),
+                                                               acc[j], 0, 0, 0);
+              accn[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, zn),
+                                                                __builtin_bit_cast(bf16x8, b),
+                                                                accn[j], 0, 0, 0);
             } else {
-              acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, za),
-                                                           __builtin_bit_cast(f16x8, b), acc,
-                                                           0, 0, 0);
-              accn = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, zn),
-                                                            __builtin_bit_cast(f16x8, b), accn,
-                                                            0, 0, 0);
+              acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, za),
+                                                              __builtin_bit_cast(f16x8, b),
+                                                              acc[j], 0, 0, 0);
+              accn[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, zn),
+                                                               __builtin_bit_cast(f16x8, b),
+                                                               accn[j], 0, 0, 0);
             }
           }
         }
       }
+    }
+
+    // ---- randomness of the next step while the matrix cores work (the
+    // buffer written was last read before the previous step's barriers)
+    if (s + 1 < nsteps) {
+      if ((s + 1) % kAccChunk == 0) draw_uniforms(s + 1);
+      draw_normals(cb ^ 1, (uint32_t)(a.step0 + s + 1));
+    }
+
+#pragma unroll
+    for (int j = 0; j < NBW; ++j)
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) {
-        const float inc = F32 ? (acc[jj] + accn[jj]) + (acc2[jj] + acc3[jj])
-                              : 0.5f * (acc[jj] - accn[jj]);
+        const float inc = F32 ? (acc[j][jj] + accn[j][jj]) + (acc2[j][jj] + acc3[j][jj])
+                              : 0.5f * (acc[j][jj] - accn[j][jj]);
         pn[j][jj] = ph[j][jj] + inc;
       }
-    }
 
     // ---- exchange old and new fields for the stencil
 #pragma unroll
@@ -318,34 +332,45 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
         xn[(4 * g + jj) * XS + col[j]] = pn[j][jj];
       }
 
-    // ---- randomness of the next step, overlapping the matrix-core work
-    if (s + 1 < nsteps) {
-      if ((s + 1) % kAccChunk == 0) draw_uniforms(s + 1);
-      draw_normals(cb ^ 1, (uint32_t)(a.step0 + s + 1));
-    }
     __syncthreads();
 
-    // ---- per-site terms: tempered -> (dS, dU0); constrained -> (S', dU0)
+    // ---- per-site terms: tempered -> (dS, dU0); constrained -> (S', dU0).
+    // Neighbour values of all owned sites are read first (one LDS round
+    // trip); columns beyond d contribute zero.
     float r0[4] = {0.f, 0.f, 0.f, 0.f}, r1[4] = {0.f, 0.f, 0.f, 0.f};
+    {
+      float n1n[NBW][4], n0n[NBW][4], n1o[NBW][4], n0o[NBW][4];
 #pragma unroll
-    for (int j = 0; j < NBW; ++j) {
-      if (!cval[j]) continue;
+      for (int j = 0; j < NBW; ++j)
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int rb = (4 * g + jj) * XS;
-        const float f = ph[j][jj], fn = pn[j][jj];
-        const float a1n = xn[rb + y1[j]] - fn, a0n = xn[rb + y0[j]] - fn;
-        const float ds = (fn - f) * (fn + f);
-        if (!constrained) {
-          const float a1o = xo[rb + y1[j]] - f, a0o = xo[rb + y0[j]] - f;
-          const float dk = (a1n - a1o) * (a1n + a1o) + (a0n - a0o) * (a0n + a0o);
-          r0[jj] += 0.5f * dk + 0.5f * a.m2 * ds + a.lam * ds * (fn * fn + f * f);
-        } else {
-          const float fn2 = fn * fn;
-          r0[jj] += 0.5f * (a1n * a1n + a0n * a0n) + 0.5f * a.m2 * fn2 + a.lam * (fn2 * fn2);
+        for (int jj = 0; jj < 4; ++jj) {
+          const int rb = (4 * g + jj) * XS;
+          n1n[j][jj] = xn[rb + y1[j]];
+          n0n[j][jj] = xn[rb + y0[j]];
+          if constexpr (!constrained) {
+            n1o[j][jj] = xo[rb + y1[j]];
+            n0o[j][jj] = xo[rb + y0[j]];
+          }
         }
-        r1[jj] += 0.5f * ds;
-      }
+#pragma unroll
+      for (int j = 0; j < NBW; ++j)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const float f = ph[j][jj], fn = pn[j][jj];
+          const float a1n = n1n[j][jj] - fn, a0n = n0n[j][jj] - fn;
+          const float ds = (fn - f) * (fn + f);
+          float t0;
+          if constexpr (!constrained) {
+            const float a1o = n1o[j][jj] - f, a0o = n0o[j][jj] - f;
+            const float dk = (a1n - a1o) * (a1n + a1o) + (a0n - a0o) * (a0n + a0o);
+            t0 = 0.5f * dk + 0.5f * a.m2 * ds + a.lam * ds * (fn * fn + f * f);
+          } else {
+            const float fn2 = fn * fn;
+            t0 = 0.5f * (a1n * a1n + a0n * a0n) + 0.5f * a.m2 * fn2 + a.lam * (fn2 * fn2);
+          }
+          r0[jj] += cval[j] ? t0 : 0.f;
+          r1[jj] += cval[j] ? 0.5f * ds : 0.f;
+        }
     }
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
@@ -373,7 +398,7 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
       const int ti = base + lane;
       if (ti < n) {
         const float lu = lus[(s / kAccChunk) & 1][s % kAccChunk][lane];
-        if (!constrained) {
+        if constexpr (!constrained) {
           const float la = -q1 - beta * q0;
           accept = lu < la;
         } else {
@@ -460,24 +485,29 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
   }
 }
 
-template <int DP, int W>
-int launch_dp(const MutateArgs& a, int precision, hipStream_t s) {
+template <int DP, int W, int KIND>
+int launch_kind(const MutateArgs& a, int precision, hipStream_t s) {
   const unsigned grid = (unsigned)((a.n + 15) / 16);
   const dim3 block(64 * W);
   switch (precision) {
     case PHI4_FP32:
-      mutate_kernel<Cfg<DP, W, PHI4_FP32>><<<grid, block, 0, s>>>(a);
+      mutate_kernel<Cfg<DP, W, PHI4_FP32, KIND>><<<grid, block, 0, s>>>(a);
       break;
     case PHI4_BF16:
-      mutate_kernel<Cfg<DP, W, PHI4_BF16>><<<grid, block, 0, s>>>(a);
+      mutate_kernel<Cfg<DP, W, PHI4_BF16, KIND>><<<grid, block, 0, s>>>(a);
       break;
     case PHI4_FP16:
-      mutate_kernel<Cfg<DP, W, PHI4_FP16>><<<grid, block, 0, s>>>(a);
+      mutate_kernel<Cfg<DP, W, PHI4_FP16, KIND>><<<grid, block, 0, s>>>(a);
       break;
     default:
       return PHI4_EINVAL;
   }
   return PHI4_OK;
+}
+
+template <int DP, int W>
+int launch_dp(const MutateArgs& a, int precision, hipStream_t s) {
+  return a.kind == 1 ? launch_kind<DP, W, 1>(a, precision, s) : launch_kind<DP, W, 0>(a, precision, s);
 }
 
 }  // namespace
