@@ -434,6 +434,7 @@ int smc_init(const phi4_smc_config* cfg, float* phi, float* S, void* workspace,
   h->cur = 0;
   h->plan = cov_plan(h->n, h->d);
   smc_carve(*cfg, workspace, &h->sb);
+  launch_cov_init(h->sb.part, h->plan, h->stream);
   int rc = alloc_pinned(h, sizeof(SmcState));
   if (rc) {
     delete h;
@@ -567,6 +568,7 @@ int ns_init(const phi4_ns_config* cfg, float* phi, float* S, void* workspace,
   h->n_steps = cfg->n_steps;
   h->ns = *cfg;
   ns_carve(*cfg, workspace, h);
+  launch_cov_init(h->part, h->nplan, h->stream);
   int rc = alloc_pinned(h, sizeof(NsState));
   if (rc) {
     delete h;
@@ -828,6 +830,7 @@ int phi4_covariance(const float* phi, const int32_t* rows, int32_t N, int32_t d,
   step_carve(N, d, workspace, &b);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const CovPlan plan = cov_plan(N, d);
+  launch_cov_init(b.part, plan, s);
   launch_cov_partials(phi, rows, plan, b.part, nullptr, s);
   FactorArgs fa = {};
   fa.part = b.part;

@@ -316,7 +316,35 @@ struct CovPlan {
   int chunk;    // particles per chunk (multiple of 4)
 };
 CovPlan cov_plan(int n, int d);
+// Covariance work area (one float buffer): per-chunk float32 partials of
+// M2 and of the first moments, their float64 sums over the chunks, and one
+// arrival counter per block (zero between launches, see launch_cov_init).
+struct CovWork {
+  float* part;    // chunks * blocks * 256
+  float* part1;   // chunks * nb * 16
+  double* fin;    // blocks * 256: M2 summed over the chunks
+  double* fin1;   // nb * 16: first moments summed over the chunks
+  int32_t* cnt;   // blocks
+};
+__host__ __device__ inline CovWork cov_work(const float* base, const CovPlan& p) {
+  float* b = const_cast<float*>(base);
+  CovWork w;
+  size_t o = (size_t)p.chunks * p.blocks * 256;
+  w.part = b;
+  w.part1 = b + o;
+  o += (size_t)p.chunks * p.nb * 16;
+  o = (o + 1) & ~(size_t)1;                 // 8-byte alignment for the sums
+  w.fin = reinterpret_cast<double*>(b + o);
+  o += 2 * (size_t)p.blocks * 256;
+  w.fin1 = reinterpret_cast<double*>(b + o);
+  o += 2 * (size_t)p.nb * 16;
+  w.cnt = reinterpret_cast<int32_t*>(b + o);
+  return w;
+}
 size_t cov_partial_floats(const CovPlan& p);
+// Zeroes the arrival counters (once per work area; the reducing workgroup of
+// each launch leaves them at zero again).
+void launch_cov_init(float* part, const CovPlan& p, hipStream_t s);
 void launch_cov_partials(const float* phi, const int32_t* rows, const CovPlan& p, float* part,
                          const int32_t* done, hipStream_t s);
 // Reduces the partials, forms sigma (d*d doubles, written if sigma_out),

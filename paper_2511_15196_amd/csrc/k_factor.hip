@@ -12,11 +12,11 @@
 //
 // Factor: tau = 1e-10 tr(Sigma) / d is added to the diagonal and multiplied
 // by 100 after each failed factorisation (at most five retries).  For
-// d <= 64 one wave factorises in registers (lane i owns row i, right-looking
-// outer-product sweep, column broadcast through LDS, no workgroup barriers);
-// larger d is factorised right-looking in 64-column panels: the diagonal
-// block in LDS in outer-product form, the panel below it solved row by row
-// and the trailing matrix updated from LDS.  The scaled factor is emitted
+// d <= 64 one workgroup forms Sigma from the chunk sums and factorises it
+// right-looking in 16-column panels (cov_factor_kernel); larger d is
+// factorised right-looking in 64-column panels: the diagonal block in LDS in
+// outer-product form, the panel below it solved row by row and the trailing
+// matrix updated from LDS.  The scaled factor is emitted
 // transposed in float32 for the mutation kernel: Bt[k*d + c] = eps * L[c][k].
 #include <utility>
 
@@ -31,6 +31,9 @@ constexpr int kFT = 1024;    // threads of the large-d factor kernel
 constexpr int kPanelRows = 128;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMaxChunks = 32;   // particle chunks per covariance block (at most)
 
 __device__ __forceinline__ int blk_of(int bi, int bj) { return bi * (bi + 1) / 2 + bj; }
 
@@ -86,20 +89,54 @@ __global__ __launch_bounds__(64) void cov_partial_kernel(const float* __restrict
       m1 += a;
     }
   }
-  float* out = part + ((size_t)chunk * p.blocks + blk) * 256;
+  const CovWork w = cov_work(part, p);
+  float* out = w.part + ((size_t)chunk * p.blocks + blk) * 256;
 #pragma unroll
   for (int jj = 0; jj < 4; ++jj) out[(4 * g + jj) * 16 + i] = acc[jj];
   if (bi == bj) {
     m1 += __shfl_xor(m1, 16, 64);
     m1 += __shfl_xor(m1, 32, 64);
-    if (g == 0) part[(size_t)p.chunks * p.blocks * 256 + (size_t)chunk * p.nb * 16 + sr] = m1;
+    if (g == 0) w.part1[(size_t)chunk * p.nb * 16 + sr] = m1;
   }
+  // The last chunk of this block to arrive sums the block's partials over the
+  // chunks in chunk order (float64) and resets the counter; the others exit.
+  __threadfence();
+  int old = 0;
+  if (lane == 0) old = atomicAdd(&w.cnt[blk], 1);
+  old = __builtin_amdgcn_readfirstlane(old);
+  if (old != p.chunks - 1) return;
+  __threadfence();
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int e = lane + 64 * t;
+    float x[kMaxChunks];
+#pragma unroll
+    for (int c = 0; c < kMaxChunks; ++c)
+      x[c] = w.part[((size_t)min(c, p.chunks - 1) * p.blocks + blk) * 256 + e];
+    double m2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < kMaxChunks; ++c) m2 += c < p.chunks ? (double)x[c] : 0.0;
+    w.fin[(size_t)blk * 256 + e] = m2;
+  }
+  if (bi == bj && lane < 16) {
+    float x[kMaxChunks];
+#pragma unroll
+    for (int c = 0; c < kMaxChunks; ++c)
+      x[c] = w.part1[(size_t)min(c, p.chunks - 1) * p.nb * 16 + 16 * bi + lane];
+    double m = 0.0;
+#pragma unroll
+    for (int c = 0; c < kMaxChunks; ++c) m += c < p.chunks ? (double)x[c] : 0.0;
+    w.fin1[16 * bi + lane] = m;
+  }
+  if (lane == 0) w.cnt[blk] = 0;
 }
 
-// Sigma from the partials: one thread per lower entry (i, j); the chunk
-// partials of M2 and of the first moments are summed in float64 in a fixed
-// order, Sigma = (M2 - m1_i m1_j / N) / (N - 1), written symmetric.
-constexpr int kMaxChunks = 32;
+__global__ void cov_init_kernel(int32_t* cnt, int blocks) {
+  for (int i = threadIdx.x; i < blocks; i += blockDim.x) cnt[i] = 0;
+}
+
+// Sigma from the chunk sums: one thread per lower entry (i, j),
+// Sigma = (M2 - m1_i m1_j / N) / (N - 1), written symmetric.
 __global__ __launch_bounds__(256) void cov_reduce_kernel(const float* __restrict__ part, CovPlan p,
                                                         double* __restrict__ sigma,
                                                         const int32_t* __restrict__ done) {
@@ -113,26 +150,8 @@ __global__ __launch_bounds__(256) void cov_reduce_kernel(const float* __restrict
   const int i = 16 * bi + r, j = 16 * bj + cc;
   const int d = p.d;
   if (i >= d || j >= d || j > i) return;
-  const float* part1 = part + (size_t)p.chunks * p.blocks * 256;
-  float v2[kMaxChunks], vi[kMaxChunks], vj[kMaxChunks];
-#pragma unroll
-  for (int c = 0; c < kMaxChunks; ++c) {
-    const int cl = min(c, p.chunks - 1);   // valid address, masked below
-    v2[c] = part[(size_t)cl * p.blocks * 256 + e];
-    vi[c] = part1[(size_t)cl * p.nb * 16 + i];
-    vj[c] = part1[(size_t)cl * p.nb * 16 + j];
-  }
-#pragma unroll
-  for (int c = 0; c < kMaxChunks; ++c)
-    if (c >= p.chunks) v2[c] = vi[c] = vj[c] = 0.f;
-  double m2 = 0.0, mi = 0.0, mj = 0.0;
-#pragma unroll
-  for (int c = 0; c < kMaxChunks; ++c) {
-    m2 += (double)v2[c];
-    mi += (double)vi[c];
-    mj += (double)vj[c];
-  }
-  const double v = (m2 - mi * mj / p.n) / (p.n - 1);
+  const CovWork w = cov_work(part, p);
+  const double v = (w.fin[e] - w.fin1[i] * w.fin1[j] / p.n) / (p.n - 1);
   sigma[(size_t)i * d + j] = v;
   sigma[(size_t)j * d + i] = v;
 }
@@ -296,138 +315,6 @@ __device__ __forceinline__ double recip_f64(double p) {
   return fma(r, e, r);
 }
 
-// Step K of the one-wave sweep below (all indices compile-time constants).
-// On entry v[K] holds D[i][K], column K sits in col[K & 1] and rp = 1/D[K][K].
-// Column K + 1 is updated first and published through LDS for the next step;
-// its pivot D[K+1][K+1] is read straight from lane K + 1's register, so the
-// next reciprocal overlaps the remaining updates of step K.
-template <int D, int K>
-__device__ __forceinline__ void chol_wave_step(double (&v)[D], double (*col)[64], int i,
-                                               double& rp, double& pown, bool& bad) {
-  constexpr int kC = 8;                       // column entries per LDS chunk
-  constexpr int m0 = (K + 2) / kC, m1 = D / kC;
-  const double* ck = col[K & 1];
-  const double f = v[K] * rp;
-  if constexpr (K + 1 < D) {
-    v[K + 1] = fma(-f, ck[K + 1], v[K + 1]);
-    col[(K + 1) & 1][i] = v[K + 1];
-    __builtin_amdgcn_sched_barrier(0);        // keep the publish ahead of the updates
-    pown = i == K + 1 ? v[K + 1] : pown;      // lane K + 1 keeps its pivot
-    const double pn = readlane64(v[K + 1], K + 1);
-    bad |= !(pn > 0.0) | isinf(pn);
-    rp = recip_f64(pn);
-  }
-  double cb[2][kC];
-  if constexpr (m0 < m1) {
-#pragma unroll
-    for (int t = 0; t < kC; ++t) cb[0][t] = ck[m0 * kC + t];
-  }
-#pragma unroll
-  for (int m = m0; m < m1; ++m) {
-    if (m + 1 < m1) {
-#pragma unroll
-      for (int t = 0; t < kC; ++t) cb[(m + 1 - m0) & 1][t] = ck[(m + 1) * kC + t];
-    }
-#pragma unroll
-    for (int t = 0; t < kC; ++t) {
-      const int j = m * kC + t;
-      if (j >= K + 2) v[j] = fma(-f, cb[(m - m0) & 1][t], v[j]);
-    }
-  }
-  __syncthreads();                            // one wave: orders the column exchange
-}
-
-template <int D, int... K>
-__device__ __forceinline__ void chol_wave_sweep(double (&v)[D], double (*col)[64], int i,
-                                                double& rp, double& pown, bool& bad,
-                                                std::integer_sequence<int, K...>) {
-  (chol_wave_step<D, K>(v, col, i, rp, pown, bad), ...);
-}
-
-// One-wave Cholesky for d <= D (D = 16, 32 or 64): lane i keeps row i of the
-// matrix in registers, padded to D x D with the identity (the padding stays
-// the identity and factors to itself).  Right-looking outer-product sweep
-// without square roots: at step K lane i applies
-// D[i][j] -= (D[i][K] / D[K][K]) D[j][K] for j > K, with column K broadcast
-// through LDS; column K + 1 is updated and published first, and the next
-// pivot is read from its lane's register, so the next reciprocal overlaps
-// the rest of step K.  At the
-// end L[i][j] = D[i][j] / sqrt(D[j][j]) below the diagonal and
-// L[i][i] = sqrt(D[i][i]), D[j][j] being the pivot of step j.  Entries above
-// the diagonal are carried along unused.
-template <int D>
-__global__ __launch_bounds__(64) void factor_wave_kernel(FactorArgs a) {
-  if (a.done && *a.done) return;
-  __shared__ double M[D][D + 1];   // the matrix padded with the identity
-  __shared__ double col[2][64];
-  const int d = a.plan.d;
-  const int i = threadIdx.x;
-  const bool rv = i < d;
-  double* sig = a.sigma_out;
-  const double* src = a.sigma_in ? a.sigma_in : sig;
-  // stage the matrix (clamped valid addresses, all loads of a batch in flight)
-  constexpr int kPer = D * D / 64;                // entries per lane, all in flight
-  {
-    double x[kPer];
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = q * 64 + i, r = e / D, cc = e % D;
-      x[q] = src[(size_t)min(r, d - 1) * d + min(cc, d - 1)];
-    }
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = q * 64 + i, r = e / D, cc = e % D;
-      const bool in = r < d && cc < d;
-      M[r][cc] = in ? x[q] : (r == cc ? 1.0 : 0.0);
-      if (a.sigma_in && in) sig[(size_t)r * d + cc] = x[q];
-    }
-  }
-  __syncthreads();
-  const int ir = min(i, D - 1);   // lanes beyond D mirror row D - 1, unused
-  const double tr = wave_red<kSum>(rv ? M[ir][ir] : 0.0);
-  double tau = 1e-10 * tr / d;
-  double v[D], pown = 1.0;
-  bool ok = false;
-  for (int attempt = 0; attempt < 6 && !ok; ++attempt) {
-    if (attempt) tau *= 100.0;
-    // row i plus tau on the diagonal
-#pragma unroll
-    for (int j = 0; j < D; ++j) v[j] = M[ir][j] + ((rv && i == j) ? tau : 0.0);
-    pown = i == 0 ? v[0] : 1.0;
-    col[0][i] = v[0];
-    __syncthreads();
-    const double p0 = readlane64(v[0], 0);
-    bool bad = !(p0 > 0.0) | isinf(p0);
-    double rp = recip_f64(p0);
-    chol_wave_sweep<D>(v, col, i, rp, pown, bad, std::make_integer_sequence<int, D>{});
-    ok = !bad;
-    __syncthreads();
-  }
-  if (!ok) {
-    if (i == 0 && a.err_out) *a.err_out = PHI4_ECHOL;
-    return;
-  }
-  // 1 / sqrt(pivot j) from lane j, broadcast through LDS
-  const double sq = sqrt(pown);
-  col[0][i] = 1.0 / sq;
-  __syncthreads();
-  const double eps = a.Bt ? *a.eps_ptr : 0.0;
-#pragma unroll
-  for (int j = 0; j < D; ++j) {
-    const double l = j < i ? v[j] * col[0][j] : (j == i ? sq : 0.0);
-    if (i < D) M[i][j] = l;
-    // Bt[k][c] = eps L[c][k]: this entry is L[i][j] -> Bt[j][i] (coalesced over lanes)
-    if (a.Bt && rv && j < d) a.Bt[(size_t)j * a.ldb + i] = (float)(eps * l);
-  }
-  __syncthreads();
-  // the float64 factor row by row from LDS (coalesced)
-  if (a.A && rv) {
-#pragma unroll 8
-    for (int r = 0; r < d; ++r) a.A[(size_t)r * d + i] = M[r][i];
-  }
-  if (i == 0 && a.tau_out) *a.tau_out = tau;
-}
-
 // ------------------------------------------------ fused small-d kernel
 
 constexpr int kCF = 512;   // threads of the fused covariance + factor kernel
@@ -441,46 +328,55 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Step K of a 16-column panel sweep by one wave: lane i holds D[i][c0 + q]
-// in v[q]; column c0 + K sits in col[K & 1]; rp = 1 / D[c0+K][c0+K].
+// in v[q], rp = 1 / D[c0+K][c0+K] and cn[j] = D[c0+j][c0+K] for j >= K + 2
+// (read from LDS one step ahead).  Column K + 1 is updated first, published
+// through LDS and read back at once for the next step, and its pivot comes
+// from its lane's register, so the LDS round trip and the next reciprocal
+// overlap the remaining updates of this step.
 template <int K>
-__device__ __forceinline__ void panel_step(double (&v)[16], double (*col)[64], int i, int c0,
-                                           double& rp, double& pown, bool& bad) {
-  const double* ck = col[K & 1];
+__device__ __forceinline__ void panel_step(double (&v)[16], double (&cn)[16], double* col, int i,
+                                           int c0, double& rp, double& pown, bool& bad) {
   const double f = v[K] * rp;
+  double nx[16];
   if constexpr (K + 1 < 16) {
-    v[K + 1] = fma(-f, ck[c0 + K + 1], v[K + 1]);
-    col[(K + 1) & 1][i] = v[K + 1];            // publish column c0 + K + 1 early
-    __builtin_amdgcn_sched_barrier(0);
+    v[K + 1] = fma(-f, readlane64(v[K], c0 + K + 1), v[K + 1]);
+    col[i] = v[K + 1];                         // publish column c0 + K + 1
+#pragma unroll
+    for (int j = K + 3; j < 16; ++j) nx[j] = col[c0 + j];   // in order after the write
     pown = i == c0 + K + 1 ? v[K + 1] : pown;  // its pivot's lane keeps it
     const double pn = readlane64(v[K + 1], c0 + K + 1);
     bad |= !(pn > 0.0) | isinf(pn);
     rp = recip_f64(pn);
   }
 #pragma unroll
-  for (int j = K + 2; j < 16; ++j) v[j] = fma(-f, ck[c0 + j], v[j]);
-  wave_sync();
+  for (int j = K + 2; j < 16; ++j) v[j] = fma(-f, cn[j], v[j]);
+#pragma unroll
+  for (int j = K + 3; j < 16; ++j) cn[j] = nx[j];
+  __builtin_amdgcn_sched_barrier(0);   // keep the next step's uses after this step's work
 }
 
 template <int... K>
-__device__ __forceinline__ void panel_sweep(double (&v)[16], double (*col)[64], int i, int c0,
-                                            double& rp, double& pown, bool& bad,
+__device__ __forceinline__ void panel_sweep(double (&v)[16], double (&cn)[16], double* col,
+                                            int i, int c0, double& rp, double& pown, bool& bad,
                                             std::integer_sequence<int, K...>) {
-  (panel_step<K>(v, col, i, c0, rp, pown, bad), ...);
+  (panel_step<K>(v, cn, col, i, c0, rp, pown, bad), ...);
 }
 
-// Covariance from the partials and its jittered Cholesky factor in one
+// Covariance from the chunk sums and its jittered Cholesky factor in one
 // workgroup, for d <= D (D = 16, 32, 64; the matrix is padded to D x D with
-// the identity).  The chunk partials are summed in float64 in chunk order,
-// Sigma = (M2 - m1_i m1_j / N) / (N - 1), into LDS (and sigma_out).  The
-// factor is right-looking in 16-column panels: wave 0 sweeps a panel in
-// registers (lane = row, outer-product steps, pivots read from their lane),
-// then every wave applies the rank-16 update to the trailing lower triangle.
+// the identity): Sigma = (M2 - m1_i m1_j / N) / (N - 1) into LDS (and
+// sigma_out).  The factor is right-looking in 16-column panels: wave 0
+// sweeps a panel in registers (lane = row, outer-product steps, columns
+// broadcast through LDS one step ahead, pivots read from their lanes'
+// registers), then the waves
+// apply the rank-16 update of the trailing lower triangle on FP64 MFMA,
+// one 16 x 16 tile each.
 template <int D>
 __global__ __launch_bounds__(kCF) void cov_factor_kernel(FactorArgs a) {
   if (a.done && *a.done) return;
   __shared__ double M[D][D + 1];
   __shared__ double Ms[D][D + 1];   // the covariance again, for retries
-  __shared__ double col[2][64];
+  __shared__ double col[64];        // column broadcast of the panel sweep
   __shared__ double m1s[64];
   __shared__ double rs[64];
   __shared__ int flag;
@@ -504,26 +400,14 @@ __global__ __launch_bounds__(kCF) void cov_factor_kernel(FactorArgs a) {
     __syncthreads();
     for (int e = tid; e < d * d; e += kCF) sig[e] = M[e / d][e % d];
   } else {
-    const float* part1 = a.part + (size_t)p.chunks * p.blocks * 256;
-    if (tid < 64) {
-      float x[kMaxChunks];
-#pragma unroll
-      for (int c = 0; c < kMaxChunks; ++c)
-        x[c] = part1[(size_t)min(c, p.chunks - 1) * p.nb * 16 + min(tid, d - 1)];
-      double m = 0.0;
-#pragma unroll
-      for (int c = 0; c < kMaxChunks; ++c) m += c < p.chunks ? (double)x[c] : 0.0;
-      m1s[tid] = m;
-    }
-    // this thread's entries: all chunk loads in flight
-    float x[EPT][kMaxChunks];
+    const CovWork w = cov_work(a.part, p);
+    if (tid < 64) m1s[tid] = w.fin1[min(tid, d - 1)];
+    double x[EPT];
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       const int e = min(tid + q * kCF, BLKS * 256 - 1);
       const int blk = min(e >> 8, p.blocks - 1);
-#pragma unroll
-      for (int c = 0; c < kMaxChunks; ++c)
-        x[q][c] = a.part[((size_t)min(c, p.chunks - 1) * p.blocks + blk) * 256 + (e & 255)];
+      x[q] = w.fin[(size_t)blk * 256 + (e & 255)];
     }
     __syncthreads();
 #pragma unroll
@@ -538,10 +422,7 @@ __global__ __launch_bounds__(kCF) void cov_factor_kernel(FactorArgs a) {
       if (j > i) continue;                      // its mirror entry writes both
       double v;
       if (i < d && j < d) {
-        double m2 = 0.0;
-#pragma unroll
-        for (int c = 0; c < kMaxChunks; ++c) m2 += c < p.chunks ? (double)x[q][c] : 0.0;
-        v = (m2 - m1s[i] * m1s[j] / p.n) / (p.n - 1);
+        v = (x[q] - m1s[i] * m1s[j] / p.n) / (p.n - 1);
         sig[(size_t)i * d + j] = v;
         sig[(size_t)j * d + i] = v;
       } else {
@@ -573,13 +454,15 @@ __global__ __launch_bounds__(kCF) void cov_factor_kernel(FactorArgs a) {
         double v[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) v[q] = M[ir][c0 + q];
-        col[0][lane] = v[0];
-        wave_sync();
+        double cn[16];
+        col[lane] = v[0];
+#pragma unroll
+        for (int j = 2; j < 16; ++j) cn[j] = col[c0 + j];
         const double p0 = readlane64(v[0], c0);
         bool bad = !(p0 > 0.0) | isinf(p0);
         double rp = recip_f64(p0);
         double pown = lane == c0 ? v[0] : 1.0;
-        panel_sweep(v, col, lane, c0, rp, pown, bad, std::make_integer_sequence<int, 16>{});
+        panel_sweep(v, cn, col, lane, c0, rp, pown, bad, std::make_integer_sequence<int, 16>{});
         // L[i][c0+q] = D[i][c0+q] / sqrt(pivot q) below the diagonal
         const double sq = sqrt(pown);
         if (lane >= c0 && lane < c0 + 16) rs[lane] = 1.0 / sq;
@@ -596,16 +479,29 @@ __global__ __launch_bounds__(kCF) void cov_factor_kernel(FactorArgs a) {
       }
       __syncthreads();
       if (flag) break;
-      // rank-16 update of the trailing lower triangle
-      const int t0 = c0 + 16, T = D - t0;
-      for (int e = tid; e < T * T; e += kCF) {
-        const int ii = e / T, jj = e - ii * T;
-        if (jj > ii) continue;
-        const int i = t0 + ii, j = t0 + jj;
-        double acc = 0.0;
+      // rank-16 update of the trailing lower triangle: tile (I, J), J <= I,
+      // of 16 x 16 gets -= L[I rows][panel] L[J rows][panel]^T (FP64 MFMA,
+      // K = 4 per instruction; operand lane p + 16k holds A[p][k] / B[k][p],
+      // result item r of lane (p, g) is row g + 4r, column p)
+      {
+        const int t0 = c0 + 16, nt = (D - t0) / 16;
+        int I = 0, J = wv;
+        while (J > I) J -= ++I;                 // wave wv -> tile (I, J) in row order
+        if (I < nt) {
+          const int pl = lane & 15, gl = lane >> 4;
+          const int r0 = t0 + 16 * I, s0 = t0 + 16 * J;
+          f64x4 acc;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc = fma(M[i][c0 + q], M[j][c0 + q], acc);
-        M[i][j] -= acc;
+          for (int r = 0; r < 4; ++r) acc[r] = M[r0 + gl + 4 * r][s0 + pl];
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const double av = -M[r0 + pl][c0 + 4 * kk + gl];   // A[i][k]: row i = pl
+            const double bv = M[s0 + pl][c0 + 4 * kk + gl];    // B[k][j]: column j = pl
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) M[r0 + gl + 4 * r][s0 + pl] = acc[r];
+        }
       }
       __syncthreads();
     }
@@ -653,7 +549,13 @@ CovPlan cov_plan(int n, int d) {
 }
 
 size_t cov_partial_floats(const CovPlan& p) {
-  return (size_t)p.chunks * p.blocks * 256 + (size_t)p.chunks * p.nb * 16;
+  size_t o = (size_t)p.chunks * p.blocks * 256 + (size_t)p.chunks * p.nb * 16;
+  o = (o + 1) & ~(size_t)1;
+  return o + 2 * (size_t)p.blocks * 256 + 2 * (size_t)p.nb * 16 + (size_t)p.blocks;
+}
+
+void launch_cov_init(float* part, const CovPlan& p, hipStream_t s) {
+  cov_init_kernel<<<1, 256, 0, s>>>(cov_work(part, p).cnt, p.blocks);
 }
 
 void launch_cov_partials(const float* phi, const int32_t* rows, const CovPlan& p, float* part,
@@ -678,10 +580,7 @@ void launch_factor(const FactorArgs& a, hipStream_t s) {
     cov_reduce_kernel<<<(entries + 255) / 256, 256, 0, s>>>(a.part, a.plan, a.sigma_out, a.done);
   }
   if (a.cov_only) return;
-  if (d <= kSmallD)
-    factor_wave_kernel<kSmallD><<<1, 64, 0, s>>>(a);
-  else
-    factor_kernel<<<1, kFT, 0, s>>>(a);
+  factor_kernel<<<1, kFT, 0, s>>>(a);
 }
 
 }  // namespace phi4
