@@ -57,7 +57,7 @@ enum { PHI4_FP32 = 0, PHI4_BF16 = 1, PHI4_FP16 = 2 };
 enum { PHI4_INIT = 1, PHI4_PROPOSE = 2, PHI4_ACCEPT = 3, PHI4_RESAMPLE = 4, PHI4_NS_PICK = 5 };
 
 /* Largest lattice the fused mutation kernel handles: d = L*L <= 256. */
-#define PHI4_MAX_SITES 256
+#define PHI4_MAX_SITES 4096
 
 /* One adaptive tempered SMC run (Sec. 2 "Particle-based Monte Carlo
  * methods" (i); App. A).  Target p_beta ~ exp(-[U0 + beta S]) with
@@ -261,13 +261,17 @@ size_t phi4_step_workspace_bytes(int32_t N, int32_t d);
  * acc_count (optional, device uint64) is incremented by the number of
  * accepted proposals.  Test outputs (optional): acc_flags[i] (uint8) = 1
  * if the last step accepted row i's proposal; prop[i*d..] = the last
- * step's proposal of row i.  precision: PHI4_FP32 / PHI4_BF16 / PHI4_FP16. */
+ * step's proposal of row i.  precision: PHI4_FP32 / PHI4_BF16 / PHI4_FP16.
+ * workspace (>= phi4_step_workspace_bytes(n, d), 256-byte aligned) is
+ * scratch for d > 256, where a step is three passes (normals, proposal
+ * product, accept) instead of the fused register-resident sweep; it may be
+ * NULL for d <= 256. */
 int phi4_mutate(const float* src, float* dst, const int32_t* rows, int32_t n, int32_t L,
                 double m2, double lambda, const float* Bt, int32_t kind, double beta,
                 double s_star, double prior_var, uint32_t seed, uint32_t run, int32_t level,
                 int32_t step0, int32_t n_steps, float zsign, int32_t precision, float* S,
                 float* absM, unsigned long long* acc_count, uint8_t* acc_flags, float* prop,
-                void* stream);
+                void* workspace, size_t workspace_bytes, void* stream);
 
 #ifdef __cplusplus
 }

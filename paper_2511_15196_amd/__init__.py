@@ -198,16 +198,22 @@ def phi4_cholesky(sigma, d, L, workspace, stream=None):
 
 def phi4_mutate(src, dst, n, L, m2, lam, Bt, kind, beta, s_star, prior_var, seed, run, level,
                 step0, n_steps, zsign, precision, S, absM=None, acc_count=None, acc_flags=None,
-                prop=None, rows=None, stream=None):
-    _require_cuda(src, dst, Bt, S, absM, acc_count, acc_flags, prop, rows)
+                prop=None, rows=None, workspace=None, stream=None):
+    _require_cuda(src, dst, Bt, S, absM, acc_count, acc_flags, prop, rows, workspace)
+    raw = None
+    if workspace is None and L * L > 256:
+        raw, workspace = _workspace(phi4_step_workspace_bytes(n, L * L), src.device)
+    wbytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
     _check(lib().phi4_mutate(_ptr(src), _ptr(dst), _ptr(rows), ctypes.c_int32(n), ctypes.c_int32(L),
                              ctypes.c_double(m2), ctypes.c_double(lam), _ptr(Bt), ctypes.c_int32(kind),
                              ctypes.c_double(beta), ctypes.c_double(s_star),
                              ctypes.c_double(prior_var), ctypes.c_uint32(seed), ctypes.c_uint32(run),
                              ctypes.c_int32(level), ctypes.c_int32(step0), ctypes.c_int32(n_steps),
                              ctypes.c_float(zsign), ctypes.c_int32(precision), _ptr(S), _ptr(absM),
-                             _ptr(acc_count), _ptr(acc_flags), _ptr(prop), _stream(stream)),
+                             _ptr(acc_count), _ptr(acc_flags), _ptr(prop), _ptr(workspace),
+                             ctypes.c_size_t(wbytes), _stream(stream)),
            "phi4_mutate")
+    del raw
 
 
 # ------------------------------------------------------ run-level helpers

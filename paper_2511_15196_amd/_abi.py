@@ -7,7 +7,7 @@ PHI4_OK, PHI4_DONE = 0, 1
 PHI4_EINVAL, PHI4_EHIP, PHI4_ECHOL, PHI4_ENONFINITE = -1, -2, -3, -4
 PHI4_FP32, PHI4_BF16, PHI4_FP16 = 0, 1, 2
 PHI4_INIT, PHI4_PROPOSE, PHI4_ACCEPT, PHI4_RESAMPLE, PHI4_NS_PICK = 1, 2, 3, 4, 5
-PHI4_MAX_SITES = 256
+PHI4_MAX_SITES = 4096
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libphi4pmc.so")
@@ -85,7 +85,8 @@ SIGNATURES = {
     "phi4_cholesky": (ctypes.c_int, [_V, _I32, _V, _PD, _V, _SZ, _V]),
     "phi4_step_workspace_bytes": (_SZ, [_I32, _I32]),
     "phi4_mutate": (ctypes.c_int, [_V, _V, _V, _I32, _I32, _D, _D, _V, _I32, _D, _D, _D, _U32,
-                                   _U32, _I32, _I32, _I32, _F, _I32, _V, _V, _V, _V, _V, _V]),
+                                   _U32, _I32, _I32, _I32, _F, _I32, _V, _V, _V, _V, _V, _V, _SZ,
+                                   _V]),
 }
 
 _lib = None

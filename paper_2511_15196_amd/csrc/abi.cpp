@@ -55,6 +55,13 @@ struct Carver {
 
 double default_eps0(int d, double eps0) { return eps0 > 0 ? eps0 : 2.38 / std::sqrt((double)d); }
 
+// Scratch of the large-lattice sweep for n particles (empty for small d).
+LargeScratch take_large(Carver& cv, int n, int d) {
+  if (d <= kFusedMaxSites || n <= 0) return LargeScratch{nullptr, nullptr, nullptr};
+  void* base = cv.take<char>(large_scratch_bytes(n, d));
+  return cv.base ? large_scratch(base, n, d) : LargeScratch{nullptr, nullptr, nullptr};
+}
+
 // ------------------------------------------------------------------ SMC
 
 struct SmcBufs {
@@ -73,6 +80,7 @@ struct SmcBufs {
   double* sigma;
   double* A;
   float* Bt;
+  LargeScratch large;
 };
 
 size_t smc_carve(const phi4_smc_config& c, void* ws, SmcBufs* b) {
@@ -95,6 +103,7 @@ size_t smc_carve(const phi4_smc_config& c, void* ws, SmcBufs* b) {
   t.sigma = cv.take<double>((size_t)d * d);
   t.A = cv.take<double>((size_t)d * d);
   t.Bt = cv.take<float>((size_t)d * d);
+  t.large = take_large(cv, n, d);
   if (b) *b = t;
   return cv.bytes();
 }
@@ -102,7 +111,7 @@ size_t smc_carve(const phi4_smc_config& c, void* ws, SmcBufs* b) {
 bool smc_valid(const phi4_smc_config* c, std::string* why) {
   if (!c) return *why = "config is NULL", false;
   const long long d = (long long)c->L * c->L;
-  if (c->L < 1 || d > PHI4_MAX_SITES) return *why = "need 1 <= L and L*L <= 256", false;
+  if (c->L < 1 || d > PHI4_MAX_SITES) return *why = "need 1 <= L and L*L <= 4096", false;
   if (c->N < 2 || c->N > (1 << 24)) return *why = "need 2 <= N <= 2^24", false;
   if (!(c->ess_frac > 0.0 && c->ess_frac <= 1.0)) return *why = "ess_frac must be in (0, 1]", false;
   if (c->n_steps < 0) return *why = "n_steps must be >= 0", false;
@@ -139,6 +148,7 @@ struct Handle {
   double* A;
   float* Bt;
   CovPlan nplan;
+  LargeScratch nlarge;
   // host mirrors
   void* pinned;  // two state copies
   hipEvent_t ev[2];
@@ -269,6 +279,7 @@ int enqueue_mutate(Handle* h) {
   m.n_steps = h->n_steps;
   m.zsign = 1.0f;
   m.done_ptr = &b.st->done;
+  m.large = b.large;
   m.S = other_S(h);
   m.absM = b.absM;
   m.acc_count = &b.st->acc;
@@ -312,7 +323,9 @@ size_t ns_carve(const phi4_ns_config& c, void* ws, Handle* h) {
   double* sigma = cv.take<double>((size_t)d * d);
   double* A = cv.take<double>((size_t)d * d);
   float* Bt = cv.take<float>((size_t)d * d);
+  const LargeScratch large = take_large(cv, k, d);
   if (h) {
+    h->nlarge = large;
     h->nst = st;
     h->absM = absM;
     h->dead = dead;
@@ -330,7 +343,7 @@ size_t ns_carve(const phi4_ns_config& c, void* ws, Handle* h) {
 bool ns_valid(const phi4_ns_config* c, std::string* why) {
   if (!c) return *why = "config is NULL", false;
   const long long d = (long long)c->L * c->L;
-  if (c->L < 1 || d > PHI4_MAX_SITES) return *why = "need 1 <= L and L*L <= 256", false;
+  if (c->L < 1 || d > PHI4_MAX_SITES) return *why = "need 1 <= L and L*L <= 4096", false;
   if (c->n_live < 3 || c->n_live > 8192) return *why = "need 3 <= n_live <= 8192", false;
   if (c->k_delete < 1 || c->k_delete > c->n_live - 2) return *why = "need 1 <= k_delete <= n_live - 2", false;
   if (c->n_steps < 0) return *why = "n_steps must be >= 0", false;
@@ -369,6 +382,7 @@ struct StepBufs {
   double* sigma;
   double* A;
   double* tau;
+  LargeScratch large;
 };
 
 size_t step_carve(int n, int d, void* ws, StepBufs* b) {
@@ -383,6 +397,7 @@ size_t step_carve(int n, int d, void* ws, StepBufs* b) {
   t.sigma = cv.take<double>((size_t)dd * dd);
   t.A = cv.take<double>((size_t)dd * dd);
   t.tau = cv.take<double>(1);
+  t.large = take_large(cv, n, dd);
   if (b) *b = t;
   return cv.bytes();
 }
@@ -435,6 +450,7 @@ int smc_init(const phi4_smc_config* cfg, float* phi, float* S, void* workspace,
   h->plan = cov_plan(h->n, h->d);
   smc_carve(*cfg, workspace, &h->sb);
   launch_cov_init(h->sb.part, h->plan, h->stream);
+  launch_large_init(h->sb.large, h->n, h->stream);
   int rc = alloc_pinned(h, sizeof(SmcState));
   if (rc) {
     delete h;
@@ -569,6 +585,7 @@ int ns_init(const phi4_ns_config* cfg, float* phi, float* S, void* workspace,
   h->ns = *cfg;
   ns_carve(*cfg, workspace, h);
   launch_cov_init(h->part, h->nplan, h->stream);
+  launch_large_init(h->nlarge, cfg->k_delete, h->stream);
   int rc = alloc_pinned(h, sizeof(NsState));
   if (rc) {
     delete h;
@@ -626,6 +643,7 @@ int ns_step(void* handle, int32_t* done_host) {
   m.n_steps = h->n_steps;
   m.zsign = 1.0f;
   m.done_ptr = &h->nst->done;
+  m.large = h->nlarge;
   m.S = h->S;
   m.absM = h->absM;
   m.acc_count = &h->nst->acc;
@@ -823,7 +841,7 @@ int phi4_covariance(const float* phi, const int32_t* rows, int32_t N, int32_t d,
                     void* workspace, size_t workspace_bytes, void* stream) {
   std::string why;
   if (N < 2 || d < 1 || d > PHI4_MAX_SITES || !phi || !sigma)
-    return fail(PHI4_EINVAL, "phi4_covariance: need N >= 2, 1 <= d <= 256");
+    return fail(PHI4_EINVAL, "phi4_covariance: need N >= 2, 1 <= d <= 4096");
   if (!ws_ok(workspace, workspace_bytes, step_carve(N, d, nullptr, nullptr), &why))
     return fail(PHI4_EINVAL, "phi4_covariance: " + why);
   StepBufs b;
@@ -876,7 +894,8 @@ int phi4_mutate(const float* src, float* dst, const int32_t* rows, int32_t n, in
                 double lambda, const float* Bt, int32_t kind, double beta, double s_star,
                 double prior_var, uint32_t seed, uint32_t run, int32_t level, int32_t step0,
                 int32_t n_steps, float zsign, int32_t precision, float* S, float* absM,
-                unsigned long long* acc_count, uint8_t* acc_flags, float* prop, void* stream) {
+                unsigned long long* acc_count, uint8_t* acc_flags, float* prop, void* workspace,
+                size_t workspace_bytes, void* stream) {
   const long long d = (long long)L * L;
   if (n < 0 || L < 1 || d > PHI4_MAX_SITES || n_steps < 0 || (kind != 0 && kind != 1))
     return fail(PHI4_EINVAL, "phi4_mutate: bad shape or kind");
@@ -910,7 +929,17 @@ int phi4_mutate(const float* src, float* dst, const int32_t* rows, int32_t n, in
   m.acc_count = acc_count;
   m.acc_flags = acc_flags;
   m.prop = prop;
-  const int rc = launch_mutate(m, precision, static_cast<hipStream_t>(stream));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (d > kFusedMaxSites && n > 0) {
+    std::string why;
+    if (!ws_ok(workspace, workspace_bytes, step_carve(n, (int)d, nullptr, nullptr), &why))
+      return fail(PHI4_EINVAL, "phi4_mutate: " + why);
+    StepBufs b;
+    step_carve(n, (int)d, workspace, &b);
+    m.large = b.large;
+    launch_large_init(b.large, n, s);
+  }
+  const int rc = launch_mutate(m, precision, s);
   if (rc) return fail(rc, "phi4_mutate: unsupported shape");
   return hip_check("phi4_mutate");
 }

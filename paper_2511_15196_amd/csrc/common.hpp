@@ -242,6 +242,15 @@ struct NsState {
 
 // ------------------------------------------------------ kernel interfaces
 
+// Scratch of the large-lattice sweep (k_large.hip) for n particles: normals
+// (n x large_dz(d) floats), proposals (n x d floats) and per-particle
+// acceptance counts (n int32, zero between sweeps).
+struct LargeScratch {
+  float* z;
+  float* prop;
+  int32_t* accp;
+};
+
 struct MutateArgs {
   const float* src;        // input rows
   float* dst;              // output rows (may equal src unless src_rows is set)
@@ -272,11 +281,20 @@ struct MutateArgs {
   unsigned long long* prop_count;
   uint8_t* acc_flags;      // test output (optional), indexed by tile slot
   float* prop;             // test output (optional), indexed by tile slot
+  LargeScratch large;      // scratch of the d > kFusedMaxSites path
 };
 
-// k_mutate.hip
+// k_mutate.hip (fused sweep, d <= kFusedMaxSites; larger d goes to k_large.hip)
+constexpr int kFusedMaxSites = 256;
 int launch_mutate(const MutateArgs& a, int precision, hipStream_t s);
 int mutate_supported(int d, int precision);
+
+// k_large.hip: per-step passes for d > kFusedMaxSites (scratch: LargeScratch).
+int large_dz(int d);
+size_t large_scratch_bytes(int n, int d);
+LargeScratch large_scratch(void* base, int n, int d);
+void launch_large_init(const LargeScratch& w, int n, hipStream_t s);
+int launch_mutate_large(const MutateArgs& a, const LargeScratch& w, int precision, hipStream_t s);
 
 // k_field.hip
 void launch_init_fields(float* phi, float* S, float* absM, int n, int L, float m2, float lam,

@@ -519,6 +519,10 @@ int mutate_supported(int d, int precision) {
 int launch_mutate(const MutateArgs& a, int precision, hipStream_t s) {
   if (!mutate_supported(a.d, precision) || a.n < 0 || a.n_steps < 0) return PHI4_EINVAL;
   if (a.n == 0) return PHI4_OK;
+  if (a.d > kFusedMaxSites) {
+    if (!a.large.z || !a.large.prop || !a.large.accp) return PHI4_EINVAL;
+    return launch_mutate_large(a, a.large, precision, s);
+  }
   const int dp = (a.d + 15) / 16 * 16;
   if (dp <= 16) return launch_dp<16, 1>(a, precision, s);
   if (dp <= 32) return launch_dp<32, 2>(a, precision, s);

@@ -66,7 +66,7 @@ def test_workspace_sizes_and_validation():
     good = P.SmcConfig(L=8, N=4096, m2=-4.0, lambda_=8.0, ess_frac=0.5, n_steps=20,
                        acc_target=0.3, eps0=0.0, seed=0, run=0, precision=0)
     assert P.smc_workspace_bytes(good) > 4096 * 64 * 4
-    for bad in [dict(L=17), dict(N=1), dict(ess_frac=0.0), dict(ess_frac=1.5), dict(precision=7),
+    for bad in [dict(L=65), dict(N=1), dict(ess_frac=0.0), dict(ess_frac=1.5), dict(precision=7),
                 dict(n_steps=-1)]:
         cfg = P.SmcConfig(**{**{f: getattr(good, f) for f, _ in good._fields_}, **bad})
         assert P.smc_workspace_bytes(cfg) == 0
@@ -77,7 +77,9 @@ def test_workspace_sizes_and_validation():
     ns.k_delete = 4095
     assert P.ns_workspace_bytes(ns) == 0
     assert P.phi4_step_workspace_bytes(4096, 64) > 0
-    assert P.phi4_step_workspace_bytes(16, 300) == 0
+    assert P.phi4_step_workspace_bytes(16, 4097) == 0
+    # the large-lattice sweep needs scratch for normals, proposals and counts
+    assert P.phi4_step_workspace_bytes(64, 1024) > 64 * 1024 * 8
 
 
 def test_invalid_calls_fail_before_touching_the_gpu():

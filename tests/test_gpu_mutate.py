@@ -1,4 +1,8 @@
-"""GPU parity of the fused random-walk Metropolis kernel against the oracle.
+"""GPU parity of the random-walk Metropolis sweep against the oracle.
+
+Lattices up to d = 256 run the fused register-resident sweep; larger ones
+(d = 324, 576, 1024 here, with ragged 64 x 64 tiles) run the three-pass
+form (normals, proposal product, accept); both are held to the same bars.
 
 The proposal product is checked against the oracle's float64 product of the
 same (rounded) operands, the Metropolis decisions against the oracle's
@@ -81,7 +85,8 @@ def product_tolerance(z, B, prop):
     return 4 * d * 2.0 ** -24 * mag + 2.0 ** -23 * np.abs(prop) + 1e-30
 
 
-@pytest.mark.parametrize("L,n", [(1, 33), (2, 50), (4, 256), (8, 1000), (10, 300), (16, 517)])
+@pytest.mark.parametrize("L,n", [(1, 33), (2, 50), (4, 256), (8, 1000), (10, 300), (16, 517),
+                                 (17, 90), (18, 70), (32, 130)])
 @pytest.mark.parametrize("precision", ["fp32", "bf16", "fp16"])
 def test_proposal_product(L, n, precision):
     """phi' - phi = B z on MFMA vs the float64 product of the same rounded operands."""
@@ -112,7 +117,7 @@ def test_proposal_uses_oracle_stream_fp32():
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16", "fp16"])
-@pytest.mark.parametrize("L", [4, 8, 16])
+@pytest.mark.parametrize("L", [4, 8, 16, 18, 32])
 def test_increment_is_odd_bitwise(precision, L):
     n = 64
     zero = np.zeros((n, L * L), dtype=np.float32)
@@ -130,7 +135,8 @@ def oracle_tempered(phi, prop, beta, L, seed, run, level, step, rows, m2=-4.0, l
 
 
 @pytest.mark.parametrize("L,n,beta", [(4, 256, 0.0), (8, 4096, 0.3), (8, 1000, 1.0),
-                                      (10, 333, 0.7), (16, 2000, 0.5)])
+                                      (10, 333, 0.7), (16, 2000, 0.5), (17, 300, 0.5),
+                                      (18, 300, 0.5), (32, 200, 0.5)])
 def test_tempered_decisions(L, n, beta):
     say("tempered", L, n, beta)
     phi = synth.broken_phase_fields(n, n, L)
@@ -152,8 +158,9 @@ def test_tempered_decisions(L, n, beta):
     assert r["acc"] == int(r["flags"].sum())
 
 
-def test_constrained_decisions():
-    L, n, pv = 8, 3000, 4.0
+@pytest.mark.parametrize("L,n", [(8, 3000), (17, 400), (32, 150)])
+def test_constrained_decisions(L, n):
+    pv = 4.0
     phi = synth.broken_phase_fields(77, n, L, v=0.2, noise=0.5)
     S0 = oact.action(phi.astype(np.float64), L, -4.0, 8.0)
     s_star = float(np.float32(np.median(S0)))
@@ -171,8 +178,9 @@ def test_constrained_decisions():
     assert np.array_equal(r["dst"], want)
 
 
-def test_row_list_in_place():
-    L, n = 8, 600
+@pytest.mark.parametrize("L", [8, 17, 24])
+def test_row_list_in_place(L):
+    n = 600
     phi = synth.broken_phase_fields(3, n, L)
     rows = synth.rng(4).choice(n, 250, replace=False).astype(np.int32)
     Bt32, B = factor(L, 8)
@@ -186,7 +194,8 @@ def test_row_list_in_place():
     assert (dec != r["flags"]).sum() <= 1
 
 
-@pytest.mark.parametrize("L,n,steps", [(4, 256, 10), (8, 2048, 20), (16, 512, 40)])
+@pytest.mark.parametrize("L,n,steps", [(4, 256, 10), (8, 2048, 20), (16, 512, 40),
+                                       (17, 200, 5), (32, 128, 5)])
 def test_multi_step_sweep_tracks_oracle(L, n, steps):
     """n fused steps vs the oracle stepping the same streams in float64."""
     say("sweep", L, n, steps)
@@ -209,8 +218,8 @@ def test_multi_step_sweep_tracks_oracle(L, n, steps):
                   <= 1e-5 * scale)
 
 
-def test_empty_and_zero_steps():
-    L = 8
+@pytest.mark.parametrize("L", [8, 18])
+def test_empty_and_zero_steps(L):
     phi = synth.fields(1, 40, L)
     Bt32, _ = factor(L, 1)
     r = run_kernel(phi, L, Bt32, n_steps=0)
