@@ -187,7 +187,18 @@ int logz(void* handle, double* logz_host, double* stderr_host);
  * out_host[9] = 1 once the run is complete, else 0. */
 int phi4_observables(void* handle, double* out_host);
 
-/* Kernel timing: while enabled, every fused mutation launch of
+/* Form of the Metropolis sweep of smc_mutate / smc_run / ns_step:
+ * PHI4_SWEEP_AUTO (default) runs the fused register-resident sweep for
+ * d <= 256 and three passes per step (normals, proposal product, accept)
+ * above; PHI4_SWEEP_FUSED and PHI4_SWEEP_PASSES force one form
+ * (PHI4_SWEEP_FUSED only for d <= 256).  Both forms draw the same Philox
+ * streams and take the same decisions up to float32 rounding. */
+#define PHI4_SWEEP_AUTO 0
+#define PHI4_SWEEP_FUSED 1
+#define PHI4_SWEEP_PASSES 2
+int phi4_set_sweep(void* handle, int32_t form);
+
+/* Kernel timing: while enabled, every mutation launch of
  * smc_mutate / smc_run / ns_step is bracketed by HIP events on the handle's
  * stream (the no-op launch smc_run enqueues after the final sweep is not
  * counted). */

@@ -126,6 +126,13 @@ def phi4_observables(h):
     return dict(zip(OBSERVABLE_NAMES, list(out)))
 
 
+SWEEPS = {"auto": 0, "fused": 1, "passes": 2}
+
+
+def phi4_set_sweep(h, form="auto"):
+    _check(lib().phi4_set_sweep(h, ctypes.c_int32(SWEEPS[form])), "phi4_set_sweep")
+
+
 def phi4_set_timing(h, enabled=True):
     _check(lib().phi4_set_timing(h, ctypes.c_int32(1 if enabled else 0)), "phi4_set_timing")
 
@@ -222,7 +229,7 @@ class SMC:
     """One adaptive tempered SMC run with torch-owned device buffers."""
 
     def __init__(self, L, N, m2, lam, ess_frac=0.5, n_steps=10, acc_target=0.3, eps0=0.0,
-                 seed=0, run=0, precision="fp32", device="cuda"):
+                 seed=0, run=0, precision="fp32", sweep="auto", device="cuda"):
         import torch
         self.cfg = SmcConfig(L=L, N=N, m2=m2, lambda_=lam, ess_frac=ess_frac, n_steps=n_steps,
                              acc_target=acc_target, eps0=eps0, seed=seed, run=run,
@@ -235,6 +242,8 @@ class SMC:
         self.S = torch.empty(N, dtype=torch.float32, device=device)
         self._raw, self.workspace = _workspace(nbytes, device)
         self.h = smc_init(self.cfg, self.phi, self.S, self.workspace)
+        if sweep != "auto":
+            phi4_set_sweep(self.h, sweep)
 
     def run(self, max_levels=10000):
         return smc_run(self.h, max_levels)
@@ -264,7 +273,8 @@ class NS:
     """One nested-sampling run with torch-owned device buffers."""
 
     def __init__(self, L, n_live, k_delete, n_steps, m2, lam, prior_var=4.0, term_frac=1e-3,
-                 acc_target=0.3, eps0=0.0, seed=0, run=0, precision="fp32", device="cuda"):
+                 acc_target=0.3, eps0=0.0, seed=0, run=0, precision="fp32", sweep="auto",
+                 device="cuda"):
         import torch
         self.cfg = NsConfig(L=L, n_live=n_live, k_delete=k_delete, n_steps=n_steps, m2=m2,
                             lambda_=lam, prior_var=prior_var, term_frac=term_frac,
@@ -278,6 +288,8 @@ class NS:
         self.S = torch.empty(n_live, dtype=torch.float32, device=device)
         self._raw, self.workspace = _workspace(nbytes, device)
         self.h = ns_init(self.cfg, self.phi, self.S, self.workspace)
+        if sweep != "auto":
+            phi4_set_sweep(self.h, sweep)
 
     def run(self, max_iter=1000000, sync_every=8):
         it = 0

@@ -74,6 +74,7 @@ SIGNATURES = {
     "logz": (ctypes.c_int, [_V, _PD, _PD]),
     "phi4_observables": (ctypes.c_int, [_V, _PD]),
     "phi4_set_timing": (ctypes.c_int, [_V, _I32]),
+    "phi4_set_sweep": (ctypes.c_int, [_V, _I32]),
     "phi4_kernel_time": (ctypes.c_int, [_V, _PD, _PI]),
     "phi4_destroy": (ctypes.c_int, [_V]),
     "phi4_last_error": (ctypes.c_char_p, []),

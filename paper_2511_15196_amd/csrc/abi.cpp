@@ -55,9 +55,9 @@ struct Carver {
 
 double default_eps0(int d, double eps0) { return eps0 > 0 ? eps0 : 2.38 / std::sqrt((double)d); }
 
-// Scratch of the large-lattice sweep for n particles (empty for small d).
+// Scratch of the three-pass sweep for n particles.
 LargeScratch take_large(Carver& cv, int n, int d) {
-  if (d <= kFusedMaxSites || n <= 0) return LargeScratch{nullptr, nullptr, nullptr};
+  if (n <= 0) return LargeScratch{nullptr, nullptr, nullptr};
   void* base = cv.take<char>(large_scratch_bytes(n, d));
   return cv.base ? large_scratch(base, n, d) : LargeScratch{nullptr, nullptr, nullptr};
 }
@@ -81,6 +81,7 @@ struct SmcBufs {
   double* A;
   float* Bt;
   LargeScratch large;
+  int32_t* bstatus;
 };
 
 size_t smc_carve(const phi4_smc_config& c, void* ws, SmcBufs* b) {
@@ -104,6 +105,7 @@ size_t smc_carve(const phi4_smc_config& c, void* ws, SmcBufs* b) {
   t.A = cv.take<double>((size_t)d * d);
   t.Bt = cv.take<float>((size_t)d * d);
   t.large = take_large(cv, n, d);
+  t.bstatus = cv.take<int32_t>(1);
   if (b) *b = t;
   return cv.bytes();
 }
@@ -133,6 +135,7 @@ struct Handle {
   // SMC
   phi4_smc_config smc;
   SmcBufs sb;
+  int sweep = PHI4_SWEEP_AUTO;
   int cur;          // 0: particles in phi/S, 1: in the workspace copy
   bool anc_pending; // resampling ancestors computed, not yet applied
   CovPlan plan;
@@ -149,6 +152,7 @@ struct Handle {
   float* Bt;
   CovPlan nplan;
   LargeScratch nlarge;
+  int32_t* nbstatus;
   // host mirrors
   void* pinned;  // two state copies
   hipEvent_t ev[2];
@@ -250,6 +254,7 @@ int enqueue_reweight(Handle* h) {
   fa.tau_out = &b.st->tau;
   fa.err_out = &b.st->err;
   fa.done = &b.st->done;
+  fa.bstatus = b.bstatus;
   launch_factor(fa, h->stream);
   return hip_check("smc_reweight_resample");
 }
@@ -280,6 +285,7 @@ int enqueue_mutate(Handle* h) {
   m.zsign = 1.0f;
   m.done_ptr = &b.st->done;
   m.large = b.large;
+  m.passes = h->sweep == PHI4_SWEEP_PASSES;
   m.S = other_S(h);
   m.absM = b.absM;
   m.acc_count = &b.st->acc;
@@ -324,8 +330,10 @@ size_t ns_carve(const phi4_ns_config& c, void* ws, Handle* h) {
   double* A = cv.take<double>((size_t)d * d);
   float* Bt = cv.take<float>((size_t)d * d);
   const LargeScratch large = take_large(cv, k, d);
+  int32_t* bstatus = cv.take<int32_t>(1);
   if (h) {
     h->nlarge = large;
+    h->nbstatus = bstatus;
     h->nst = st;
     h->absM = absM;
     h->dead = dead;
@@ -621,6 +629,7 @@ int ns_step(void* handle, int32_t* done_host) {
   fa.tau_out = &h->nst->tau;
   fa.err_out = &h->nst->err;
   fa.done = &h->nst->done;
+  fa.bstatus = h->nbstatus;
   launch_factor(fa, h->stream);
   MutateArgs m = {};
   m.src = h->phi;
@@ -644,6 +653,7 @@ int ns_step(void* handle, int32_t* done_host) {
   m.zsign = 1.0f;
   m.done_ptr = &h->nst->done;
   m.large = h->nlarge;
+  m.passes = h->sweep == PHI4_SWEEP_PASSES;
   m.S = h->S;
   m.absM = h->absM;
   m.acc_count = &h->nst->acc;
@@ -724,6 +734,16 @@ int phi4_observables(void* handle, double* out) {
   out[7] = s->tau;
   out[8] = 0.0;
   out[9] = s->done;
+  return PHI4_OK;
+}
+
+int phi4_set_sweep(void* handle, int32_t form) {
+  Handle* h = static_cast<Handle*>(handle);
+  if (!h) return fail(PHI4_EINVAL, "phi4_set_sweep: NULL handle");
+  if (form < PHI4_SWEEP_AUTO || form > PHI4_SWEEP_PASSES ||
+      (form == PHI4_SWEEP_FUSED && h->d > kFusedMaxSites))
+    return fail(PHI4_EINVAL, "phi4_set_sweep: unknown form, or fused beyond d = 256");
+  h->sweep = form;
   return PHI4_OK;
 }
 
@@ -877,6 +897,7 @@ int phi4_cholesky(const double* sigma, int32_t d, double* L, double* tau_host, v
   fa.A = L;
   fa.tau_out = b.tau;
   fa.err_out = b.status;
+  fa.bstatus = b.status + 1;
   launch_factor(fa, s);
   int rc = hip_check("phi4_cholesky");
   if (rc) return rc;

@@ -281,7 +281,8 @@ struct MutateArgs {
   unsigned long long* prop_count;
   uint8_t* acc_flags;      // test output (optional), indexed by tile slot
   float* prop;             // test output (optional), indexed by tile slot
-  LargeScratch large;      // scratch of the d > kFusedMaxSites path
+  LargeScratch large;      // scratch of the three-pass sweep
+  int32_t passes;          // 1: three passes per step even for d <= kFusedMaxSites
 };
 
 // k_mutate.hip (fused sweep, d <= kFusedMaxSites; larger d goes to k_large.hip)
@@ -381,6 +382,7 @@ struct FactorArgs {
   int32_t* err_out;
   const int32_t* done;
   int32_t cov_only;        // stop after writing sigma_out
+  int32_t* bstatus;        // scratch int of the blocked factor (d > 64): 1 = pivot failed
 };
 void launch_factor(const FactorArgs& a, hipStream_t s);
 

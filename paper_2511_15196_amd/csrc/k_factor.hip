@@ -248,6 +248,9 @@ __device__ bool chol_full(double* __restrict__ A, int d, double (*D)[kTile + 1],
 
 __global__ __launch_bounds__(kFT) void factor_kernel(FactorArgs a) {
   if (a.done && *a.done) return;
+  // behind the blocked factor this kernel only runs the jitter escalation
+  // after a failed first attempt
+  if (a.bstatus && *a.bstatus == 0) return;
   __shared__ double D[kTile][kTile + 1];
   __shared__ double P[kPanelRows][kTile + 1];
   __shared__ double shd[kFT / 64];
@@ -362,6 +365,80 @@ __device__ __forceinline__ void panel_sweep(double (&v)[16], double (&cn)[16], d
   (panel_step<K>(v, cn, col, i, c0, rp, pown, bad), ...);
 }
 
+// Right-looking Cholesky of the D x D matrix in LDS (lower part in, L out;
+// entries above the diagonal are scratch), D = 16, 32 or 64, by 512
+// threads: wave 0 sweeps each 16-column panel in registers (lane = row,
+// outer-product steps, columns broadcast through LDS one step ahead, pivots
+// read from their lanes' registers), then the waves apply the rank-16
+// update of the trailing lower triangle on FP64 MFMA, one 16 x 16 tile
+// each.  Returns false (uniformly) if a pivot is not positive and finite.
+template <int D>
+__device__ bool chol_lds(double (*M)[D + 1], double* col, double* rs, int* flag) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid == 0) *flag = 0;
+  __syncthreads();
+    for (int c0 = 0; c0 < D; c0 += 16) {
+      if (wv == 0) {
+        const int ir = min(lane, D - 1);        // lanes beyond D mirror row D - 1, unused
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = M[ir][c0 + q];
+        double cn[16];
+        col[lane] = v[0];
+#pragma unroll
+        for (int j = 2; j < 16; ++j) cn[j] = col[c0 + j];
+        const double p0 = readlane64(v[0], c0);
+        bool bad = !(p0 > 0.0) | isinf(p0);
+        double rp = recip_f64(p0);
+        double pown = lane == c0 ? v[0] : 1.0;
+        panel_sweep(v, cn, col, lane, c0, rp, pown, bad, std::make_integer_sequence<int, 16>{});
+        // L[i][c0+q] = D[i][c0+q] / sqrt(pivot q) below the diagonal
+        const double sq = sqrt(pown);
+        if (lane >= c0 && lane < c0 + 16) rs[lane] = 1.0 / sq;
+        wave_sync();
+        if (lane >= c0 && lane < D) {
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            const int j = c0 + q;
+            if (lane > j) M[lane][j] = v[q] * rs[j];
+            else if (lane == j) M[lane][j] = sq;
+          }
+        }
+        if (bad && lane == 0) *flag = 1;
+      }
+      __syncthreads();
+      if (*flag) break;
+      // rank-16 update of the trailing lower triangle: tile (I, J), J <= I,
+      // of 16 x 16 gets -= L[I rows][panel] L[J rows][panel]^T (FP64 MFMA,
+      // K = 4 per instruction; operand lane p + 16k holds A[p][k] / B[k][p],
+      // result item r of lane (p, g) is row g + 4r, column p)
+      {
+        const int t0 = c0 + 16, nt = (D - t0) / 16;
+        int I = 0, J = wv;
+        while (J > I) J -= ++I;                 // wave wv -> tile (I, J) in row order
+        if (I < nt) {
+          const int pl = lane & 15, gl = lane >> 4;
+          const int r0 = t0 + 16 * I, s0 = t0 + 16 * J;
+          f64x4 acc;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[r] = M[r0 + gl + 4 * r][s0 + pl];
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const double av = -M[r0 + pl][c0 + 4 * kk + gl];   // A[i][k]: row i = pl
+            const double bv = M[s0 + pl][c0 + 4 * kk + gl];    // B[k][j]: column j = pl
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) M[r0 + gl + 4 * r][s0 + pl] = acc[r];
+        }
+      }
+      __syncthreads();
+    }
+  const bool ok = *flag == 0;
+  __syncthreads();
+  return ok;
+}
+
 // Covariance from the chunk sums and its jittered Cholesky factor in one
 // workgroup, for d <= D (D = 16, 32, 64; the matrix is padded to D x D with
 // the identity): Sigma = (M2 - m1_i m1_j / N) / (N - 1) into LDS (and
@@ -446,66 +523,8 @@ __global__ __launch_bounds__(kCF) void cov_factor_kernel(FactorArgs a) {
       __syncthreads();
     }
     if (tid < d) M[tid][tid] += tau;
-    if (tid == 0) flag = 0;
     __syncthreads();
-    for (int c0 = 0; c0 < D; c0 += 16) {
-      if (wv == 0) {
-        const int ir = min(lane, D - 1);        // lanes beyond D mirror row D - 1, unused
-        double v[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) v[q] = M[ir][c0 + q];
-        double cn[16];
-        col[lane] = v[0];
-#pragma unroll
-        for (int j = 2; j < 16; ++j) cn[j] = col[c0 + j];
-        const double p0 = readlane64(v[0], c0);
-        bool bad = !(p0 > 0.0) | isinf(p0);
-        double rp = recip_f64(p0);
-        double pown = lane == c0 ? v[0] : 1.0;
-        panel_sweep(v, cn, col, lane, c0, rp, pown, bad, std::make_integer_sequence<int, 16>{});
-        // L[i][c0+q] = D[i][c0+q] / sqrt(pivot q) below the diagonal
-        const double sq = sqrt(pown);
-        if (lane >= c0 && lane < c0 + 16) rs[lane] = 1.0 / sq;
-        wave_sync();
-        if (lane >= c0 && lane < D) {
-#pragma unroll
-          for (int q = 0; q < 16; ++q) {
-            const int j = c0 + q;
-            if (lane > j) M[lane][j] = v[q] * rs[j];
-            else if (lane == j) M[lane][j] = sq;
-          }
-        }
-        if (bad && lane == 0) flag = 1;
-      }
-      __syncthreads();
-      if (flag) break;
-      // rank-16 update of the trailing lower triangle: tile (I, J), J <= I,
-      // of 16 x 16 gets -= L[I rows][panel] L[J rows][panel]^T (FP64 MFMA,
-      // K = 4 per instruction; operand lane p + 16k holds A[p][k] / B[k][p],
-      // result item r of lane (p, g) is row g + 4r, column p)
-      {
-        const int t0 = c0 + 16, nt = (D - t0) / 16;
-        int I = 0, J = wv;
-        while (J > I) J -= ++I;                 // wave wv -> tile (I, J) in row order
-        if (I < nt) {
-          const int pl = lane & 15, gl = lane >> 4;
-          const int r0 = t0 + 16 * I, s0 = t0 + 16 * J;
-          f64x4 acc;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) acc[r] = M[r0 + gl + 4 * r][s0 + pl];
-#pragma unroll
-          for (int kk = 0; kk < 4; ++kk) {
-            const double av = -M[r0 + pl][c0 + 4 * kk + gl];   // A[i][k]: row i = pl
-            const double bv = M[s0 + pl][c0 + 4 * kk + gl];    // B[k][j]: column j = pl
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-          }
-#pragma unroll
-          for (int r = 0; r < 4; ++r) M[r0 + gl + 4 * r][s0 + pl] = acc[r];
-        }
-      }
-      __syncthreads();
-    }
-    ok = flag == 0;
+    ok = chol_lds<D>(M, col, rs, &flag);
     __syncthreads();
   }
   if (!ok) {
@@ -523,6 +542,171 @@ __global__ __launch_bounds__(kCF) void cov_factor_kernel(FactorArgs a) {
     }
   }
   if (tid == 0 && a.tau_out) *a.tau_out = tau;
+}
+
+// ------------------------------------------------------ blocked factor
+//
+// For d > 64: right-looking Cholesky of Sigma + tau0 I in 64-column panels,
+// one kernel per stage so that every stage uses as many workgroups as it
+// has independent work: the 64 x 64 diagonal block on one workgroup
+// (chol_lds), the panel below it by rows (X L11^T = A21, one lane per row),
+// and the rank-64 update of the trailing lower tiles on FP64 MFMA.  A pivot
+// failure sets bstatus; later stages then return at once and the
+// single-workgroup factor_kernel runs the full jitter escalation from
+// tau0 (so the result follows the same rule as the first attempt).
+
+constexpr int kBT = 256;   // threads of the row-parallel stages
+
+__global__ __launch_bounds__(1024) void bf_init_kernel(const double* __restrict__ src, int d,
+                                                       double* __restrict__ tau,
+                                                       int32_t* __restrict__ status,
+                                                       const int32_t* __restrict__ done) {
+  if (done && *done) return;
+  __shared__ double shd[16];
+  double t = 0.0;
+  for (int i = threadIdx.x; i < d; i += 1024) t += src[(size_t)i * d + i];
+  t = block_reduce<kSum, 16>(t, shd);
+  if (threadIdx.x == 0) {
+    *tau = 1e-10 * t / d;
+    *status = 0;
+  }
+}
+
+// A (lower part) = src + tau I
+__global__ __launch_bounds__(256) void bf_copy_kernel(const double* __restrict__ src,
+                                                      double* __restrict__ A, int d,
+                                                      const double* __restrict__ tau,
+                                                      const int32_t* __restrict__ done) {
+  if (done && *done) return;
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long long)d * d) return;
+  const int i = (int)(e / d), j = (int)(e - (long long)i * d);
+  if (j <= i) A[e] = src[e] + (i == j ? *tau : 0.0);
+}
+
+// Diagonal block kb: factor in LDS (padded with the identity past d).
+__global__ __launch_bounds__(kCF) void bf_diag_kernel(double* __restrict__ A, int d, int kb,
+                                                      int32_t* __restrict__ status,
+                                                      const int32_t* __restrict__ done) {
+  if ((done && *done) || *status) return;
+  __shared__ double M[64][65];
+  __shared__ double col[64];
+  __shared__ double rs[64];
+  __shared__ int flag;
+  const int nb = min(64, d - kb);
+  for (int e = threadIdx.x; e < 64 * 64; e += kCF) {
+    const int r = e >> 6, c = e & 63;
+    double v = r == c ? 1.0 : 0.0;
+    if (r < nb && c <= r) v = A[(size_t)(kb + r) * d + kb + c];
+    M[r][c] = v;
+  }
+  __syncthreads();
+  if (!chol_lds<64>(M, col, rs, &flag)) {
+    if (threadIdx.x == 0) *status = 1;
+    return;
+  }
+  for (int e = threadIdx.x; e < 64 * 64; e += kCF) {
+    const int r = e >> 6, c = e & 63;
+    if (r < nb && c <= r) A[(size_t)(kb + r) * d + kb + c] = M[r][c];
+  }
+}
+
+// Panel below block kb: row i (one lane) solves x L11^T = a, column by
+// column; L11 entries are uniform over the wave (scalar loads).
+__global__ __launch_bounds__(kBT) void bf_trsm_kernel(double* __restrict__ A,
+                                                      const double* __restrict__ L11, int d,
+                                                      int kb, const int32_t* __restrict__ status,
+                                                      const int32_t* __restrict__ done) {
+  if ((done && *done) || *status) return;
+  const int i = kb + 64 + blockIdx.x * kBT + threadIdx.x;
+  const int ic = min(i, d - 1);                 // valid row, masked on the write
+  double x[64];
+#pragma unroll
+  for (int m = 0; m < 64; ++m) x[m] = A[(size_t)ic * d + kb + m];
+#pragma unroll
+  for (int m = 0; m < 64; ++m) {
+    const double* Lm = L11 + (size_t)(kb + m) * d + kb;   // row m of L11
+    x[m] = x[m] / Lm[m];
+#pragma unroll
+    for (int j = m + 1; j < 64; ++j) x[j] = fma(-x[m], L11[(size_t)(kb + j) * d + kb + m], x[j]);
+  }
+  if (i < d) {
+#pragma unroll
+    for (int m = 0; m < 64; ++m) A[(size_t)i * d + kb + m] = x[m];
+  }
+}
+
+// Trailing update A[I][J] -= X_I X_J^T for the 64 x 64 tiles (I, J), J <= I,
+// below block kb; X is the solved panel.  Wave w computes a 32 x 32 quarter
+// as 2 x 2 FP64 MFMA tiles (K = 4 per instruction).
+__global__ __launch_bounds__(256) void bf_syrk_kernel(double* __restrict__ A, int d, int kb,
+                                                      const int32_t* __restrict__ status,
+                                                      const int32_t* __restrict__ done) {
+  if ((done && *done) || *status) return;
+  __shared__ double Xi[64][65];
+  __shared__ double Xj[64][65];
+  int I = 0, J = blockIdx.x;
+  while (J > I) J -= ++I;                       // block -> tile (I, J) in row order
+  const int t0 = kb + 64;
+  const int r0 = t0 + 64 * I, s0 = t0 + 64 * J;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    const int ri = min(r0 + r, d - 1), rj = min(s0 + r, d - 1);
+    const double vi = A[(size_t)ri * d + kb + c], vj = A[(size_t)rj * d + kb + c];
+    Xi[r][c] = r0 + r < d ? vi : 0.0;
+    Xj[r][c] = s0 + r < d ? vj : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int pl = lane & 15, gl = lane >> 4;
+  const int wr = wv >> 1, wc = wv & 1;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + 32 * wr + 16 * a + gl + 4 * r, c = s0 + 32 * wc + 16 * b + pl;
+        acc[a][b][r] = A[(size_t)min(row, d - 1) * d + min(c, d - 1)];
+      }
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk)
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const double av = -Xi[32 * wr + 16 * a + pl][4 * kk + gl];
+        const double bv = Xj[32 * wc + 16 * b + pl][4 * kk + gl];
+        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[a][b], 0, 0, 0);
+      }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + 32 * wr + 16 * a + gl + 4 * r, c = s0 + 32 * wc + 16 * b + pl;
+        if (row < d && c < d && c <= row) A[(size_t)row * d + c] = acc[a][b][r];
+      }
+}
+
+// Outputs of a successful blocked factor: the upper part of A zeroed and
+// Bt[k][c] = eps L[c][k] in float32.
+__global__ __launch_bounds__(256) void bf_emit_kernel(double* __restrict__ A, int d,
+                                                      float* __restrict__ Bt, int ldb,
+                                                      const double* __restrict__ eps_ptr,
+                                                      const int32_t* __restrict__ status,
+                                                      const int32_t* __restrict__ done) {
+  if ((done && *done) || *status) return;
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long long)d * d) return;
+  const int i = (int)(e / d), j = (int)(e - (long long)i * d);
+  if (j > i) A[e] = 0.0;
+  if (Bt) {
+    const int k = i, c = j;   // Bt row k, column c
+    Bt[(size_t)k * ldb + c] = c >= k ? (float)(*eps_ptr * A[(size_t)c * d + k]) : 0.f;
+  }
 }
 
 }  // namespace
@@ -580,6 +764,24 @@ void launch_factor(const FactorArgs& a, hipStream_t s) {
     cov_reduce_kernel<<<(entries + 255) / 256, 256, 0, s>>>(a.part, a.plan, a.sigma_out, a.done);
   }
   if (a.cov_only) return;
+  if (a.bstatus && d > kSmallD) {
+    // blocked factor at tau0; the single-workgroup kernel below only runs
+    // if one of its pivots failed
+    const double* src = a.sigma_in ? a.sigma_in : a.sigma_out;
+    const unsigned nel = (unsigned)(((long long)d * d + 255) / 256);
+    bf_init_kernel<<<1, 1024, 0, s>>>(src, d, a.tau_out, a.bstatus, a.done);
+    bf_copy_kernel<<<nel, 256, 0, s>>>(src, a.A, d, a.tau_out, a.done);
+    for (int kb = 0; kb < d; kb += 64) {
+      bf_diag_kernel<<<1, kCF, 0, s>>>(a.A, d, kb, a.bstatus, a.done);
+      const int below = d - kb - 64;
+      if (below > 0) {
+        bf_trsm_kernel<<<(below + kBT - 1) / kBT, kBT, 0, s>>>(a.A, a.A, d, kb, a.bstatus, a.done);
+        const int nt = (below + 63) / 64;
+        bf_syrk_kernel<<<nt * (nt + 1) / 2, 256, 0, s>>>(a.A, d, kb, a.bstatus, a.done);
+      }
+    }
+    bf_emit_kernel<<<nel, 256, 0, s>>>(a.A, d, a.Bt, a.ldb, a.eps_ptr, a.bstatus, a.done);
+  }
   factor_kernel<<<1, kFT, 0, s>>>(a);
 }
 

@@ -519,7 +519,7 @@ int mutate_supported(int d, int precision) {
 int launch_mutate(const MutateArgs& a, int precision, hipStream_t s) {
   if (!mutate_supported(a.d, precision) || a.n < 0 || a.n_steps < 0) return PHI4_EINVAL;
   if (a.n == 0) return PHI4_OK;
-  if (a.d > kFusedMaxSites) {
+  if (a.d > kFusedMaxSites || a.passes) {
     if (!a.large.z || !a.large.prop || !a.large.accp) return PHI4_EINVAL;
     return launch_mutate_large(a, a.large, precision, s);
   }

@@ -189,7 +189,8 @@ def test_covariance_row_subset():
     assert np.max(np.abs(host(sig) - want)) <= 2e-5 * np.max(np.diag(want))
 
 
-@pytest.mark.parametrize("d,cond", [(1, 1.0), (16, 1e3), (64, 1e4), (100, 1e2), (256, 1e3)])
+@pytest.mark.parametrize("d,cond", [(1, 1.0), (16, 1e3), (64, 1e4), (100, 1e2), (256, 1e3),
+                                    (300, 1e3), (1024, 1e2)])
 def test_cholesky_matches_oracle(d, cond):
     say("chol", d)
     A = synth.spd_matrix(d + 1, d, cond=cond)
@@ -215,3 +216,21 @@ def test_cholesky_jitter_and_failure():
     with pytest.raises(P.Phi4Error) as e:
         P.phi4_cholesky(dev(np.diag([1.0, -1.0, 2.0])), 3, Lt, wsp)
     assert e.value.code == P.PHI4_ECHOL
+
+
+@pytest.mark.parametrize("d", [100, 324])
+def test_blocked_cholesky_jitter_escalation(d):
+    """Rank-deficient covariance (d > 64): the blocked first attempt fails and
+    the escalation reaches the oracle's tau and factor."""
+    L = int(round(d ** 0.5))
+    x = synth.fields(5, d // 2, L).astype(np.float64)    # rank d/2 - 1 < d
+    A = osmc.covariance(x)
+    raw, wsp = ws(P.phi4_step_workspace_bytes(2, d))
+    Lt = torch.empty((d, d), dtype=torch.float64, device=DEV)
+    tau = P.phi4_cholesky(dev(A), d, Lt, wsp)
+    want, tau0 = osmc.cholesky_jitter(A)
+    say("tau", tau, tau0)
+    assert tau == pytest.approx(tau0, rel=1e-12)
+    got = host(Lt)
+    assert np.allclose(np.triu(got, 1), 0.0)
+    assert np.max(np.abs(got - want)) <= 1e-8 * np.sqrt(np.max(np.diag(A))) * d

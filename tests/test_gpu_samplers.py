@@ -26,8 +26,9 @@ def say(*a):
     sys.stdout.flush()
 
 
-def gpu_smc(L, N, m2, lam, ess, steps, seed, precision="fp32"):
-    run = P.SMC(L, N, m2, lam, ess_frac=ess, n_steps=steps, seed=seed, precision=precision)
+def gpu_smc(L, N, m2, lam, ess, steps, seed, precision="fp32", sweep="auto"):
+    run = P.SMC(L, N, m2, lam, ess_frac=ess, n_steps=steps, seed=seed, precision=precision,
+                sweep=sweep)
     rc, levels = run.run()
     obs = run.observables()
     z = run.logz()
@@ -109,13 +110,44 @@ def test_smc_large_lattice_coupled_to_oracle():
     assert abs(g["logz"] - o["logz"]) < 0.5
 
 
-def test_ns_large_lattice_coupled_to_oracle():
-    say("ns L=17 n=700 k=350")
-    run = P.NS(17, 700, 350, 20, 1.0, 0.0, prior_var=4.0, term_frac=1e-3, seed=3)
+def test_smc_three_pass_form_coupled_to_oracle():
+    """The three-pass sweep forced at L = 4 follows the same streams."""
+    say("smc passes L=4 N=256")
+    g = gpu_smc(4, 256, -4.0, 8.0, 0.5, 10, 0, sweep="passes")
+    o = osmc.smc_run(4, -4.0, 8.0, 256, 0.5, 10, seed=0)
+    say("gpu", g, "oracle", o["logz"], o["n_levels"])
+    assert g["levels"] == o["n_levels"]
+    assert abs(g["logz"] - o["logz"]) < 0.05
+    assert abs(g["mean_abs_m"] - o["mean_abs_m"]) < 0.01
+
+
+def test_ns_three_pass_form_coupled_to_oracle():
+    """Nested sampling with the three-pass sweep forced at L = 2."""
+    say("ns passes L=2")
+    run = P.NS(2, 400, 200, 20, 1.0, 0.0, prior_var=4.0, term_frac=1e-3, seed=3,
+               sweep="passes")
     z, se = run.run()
     obs = run.observables()
     run.close()
-    o = ons.ns_run(17, 1.0, 0.0, 700, 350, 20, seed=3)
+    o = ons.ns_run(2, 1.0, 0.0, 400, 200, 20, seed=3)
     say("gpu", z, se, obs, "oracle", o["logz"], o["logz_err"], o["n_iter"])
-    assert abs(int(obs["levels"]) - o["n_iter"]) <= 2
-    assert abs(z - o["logz"]) < 2 * o["logz_err"]
+    assert int(obs["levels"]) == o["n_iter"]
+    assert abs(z - o["logz"]) < 0.05
+
+
+def test_ns_large_lattice_replicas_match_oracle():
+    """Nested sampling at L = 17 (d = 289, three-pass sweep), 40 refill steps:
+    GPU and oracle replica means of log Z within 2 sigma.  Single runs are
+    not held to each other: over ~2e6 Metropolis decisions float32 near-ties
+    decouple them, and the run-to-run spread here (sd ~1.8) is several times
+    the per-run error sqrt(H / n)."""
+    seeds = range(4)
+    g, o = [], []
+    for s in seeds:
+        run = P.NS(17, 700, 350, 40, 1.0, 0.0, prior_var=4.0, term_frac=1e-3, seed=s)
+        g.append(run.run()[0])
+        run.close()
+        o.append(ons.ns_run(17, 1.0, 0.0, 700, 350, 40, seed=s)["logz"])
+    se = math.sqrt(np.var(g, ddof=1) / len(g) + np.var(o, ddof=1) / len(o))
+    say("ns L=17 gpu", g, "oracle", o, "se", se)
+    assert abs(np.mean(g) - np.mean(o)) <= 2 * se
