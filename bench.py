@@ -45,6 +45,11 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the free-theory check and the L=16 SMC / L=32 NS workloads")
+    ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MIB",
+                    help="only copy MIB mebibytes device-to-device with torch and exit "
+                         "(calibrates the HBM byte counters of a profiler run)")
     return ap.parse_args()
 
 
@@ -92,6 +97,92 @@ def cpu_baseline():
                 logz=r["logz"])
 
 
+def free_log_z(L, m2):
+    """Exact log Z of the free theory (lambda = 0) under the N(0, I) reference:
+    -1/2 sum_k log(1 + m2 + lambda_k), lambda_k the periodic lattice-Laplacian
+    eigenvalues 4 sin^2(pi k0 / L) + 4 sin^2(pi k1 / L)."""
+    t = 0.0
+    for k0 in range(L):
+        for k1 in range(L):
+            lk = 4 * math.sin(math.pi * k0 / L) ** 2 + 4 * math.sin(math.pi * k1 / L) ** 2
+            t += math.log(1.0 + m2 + lk)
+    return -0.5 * t
+
+
+def smc_workload(P, torch, L, N, m2, lam, n_steps, precision, seed=0):
+    """One warm-up run and one timed full SMC run (seed `seed`)."""
+    smc = P.SMC(L, N, m2, lam, ess_frac=0.5, n_steps=n_steps, seed=seed, precision=precision)
+    smc.restart(seed + 1000)
+    smc.run()
+    smc.restart(seed)
+    P.phi4_kernel_time(smc.h)
+    P.phi4_set_timing(smc.h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, lv = smc.run()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, launches = P.phi4_kernel_time(smc.h)
+    obs = smc.observables()
+    out = dict(value=lv * N * n_steps / wall, levels=lv, ms_per_run=wall * 1e3,
+               logz=smc.logz(), mean_abs_m=obs["mean_abs_m"],
+               sweep_ms_per_level=kms / max(launches, 1))
+    smc.close()
+    return out
+
+
+def ns_workload(P, torch, L, n, k, n_steps, precision, iters, warm=2, seed=0):
+    """`iters` timed nested-sampling iterations after `warm` untimed ones."""
+    ns = P.NS(L, n, k, n_steps, -4.0, 8.0, prior_var=4.0, term_frac=1e-3, seed=seed,
+              precision=precision)
+    for _ in range(warm):
+        P.ns_step(ns.h, sync=False)
+    P.phi4_kernel_time(ns.h)
+    P.phi4_set_timing(ns.h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        P.ns_step(ns.h, sync=False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, launches = P.phi4_kernel_time(ns.h)
+    d = L * L
+    sweep_s = kms * 1e-3 / max(launches, 1)
+    out = dict(value=iters * k * n_steps / wall, ms_per_iter=wall / iters * 1e3,
+               sweep_ms=sweep_s * 1e3,
+               proposal_tflops_in_sweep=k * n_steps * d * (d + 1) / sweep_s / 1e12)
+    ns.close()
+    return out
+
+
+def extra_workloads(P, torch):
+    """Free-theory check of the main workload, SMC at L = 16 and NS at L = 32."""
+    ex = {}
+    fz = smc_workload(P, torch, 8, 4096, 1.0, 0.0, 20, "fp32")
+    exact = free_log_z(8, 1.0)
+    ex["free_theory_L8"] = dict(logz=fz["logz"], exact=exact, dlogz=fz["logz"] - exact,
+                                levels=fz["levels"], note="m2=1, lambda=0, N=4096, 20 steps/level; "
+                                "the gap is the method's finite-mixing bias, shared by the oracle")
+    for lam in (5.0, 8.0):
+        for prec in ("fp32", "bf16"):
+            ex[f"smc_L16_N16384_lam{lam:g}_{prec}"] = smc_workload(P, torch, 16, 16384, -4.0, lam,
+                                                                     20, prec)
+    for prec in ("fp32", "bf16"):
+        ex[f"ns_L32_n4096_k2048_{prec}"] = ns_workload(P, torch, 32, 4096, 2048, 40, prec, 8)
+    return ex
+
+
+def copy_probe(torch, mib):
+    n = int(mib * (1 << 20)) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
+                      "launches": 3}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -105,6 +196,9 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_probe > 0:
+        copy_probe(torch, args.copy_probe)
+        return
     w = WORKLOAD
     d = w["L"] ** 2
     r = timed_runs(P, torch, args.precision, args.steps, args.warmup)
@@ -144,6 +238,8 @@ def main():
         rb = timed_runs(P, torch, "bf16", max(2, args.steps // 2), 1)
         line["bf16"] = {"value": rb["pu"] / rb["wall"], "logz_seed0": rb["logz_seed0"],
                         "mutate_kernel_us": rb["kernel_ms"] / max(rb["launches"], 1) * 1e3}
+    if not args.no_extra and args.precision == "fp32":
+        line["workloads"] = extra_workloads(P, torch)
     if not args.no_cpu_baseline:
         cb = cpu_baseline()
         line["dlogz_vs_oracle_seed0"] = abs(r["logz_seed0"] - cb.pop("logz"))

@@ -82,7 +82,17 @@ struct SmcBufs {
   float* Bt;
   LargeScratch large;
   int32_t* bstatus;
+  double* bscr;
 };
+
+// Blocked-factor fields of FactorArgs from its carved scratch.
+void set_blocked(FactorArgs& fa, int32_t* bstatus, double* bscr, int d) {
+  if (blocked_attempts(d) == 0) return;   // d <= 64: one-workgroup factor
+  fa.bstatus = bstatus;
+  fa.attempts = blocked_attempts(d);
+  fa.Aspec = bscr;
+  fa.Winv = bscr + (size_t)(fa.attempts > 1 ? fa.attempts - 1 : 0) * d * d;
+}
 
 size_t smc_carve(const phi4_smc_config& c, void* ws, SmcBufs* b) {
   const int d = c.L * c.L, n = c.N;
@@ -105,7 +115,8 @@ size_t smc_carve(const phi4_smc_config& c, void* ws, SmcBufs* b) {
   t.A = cv.take<double>((size_t)d * d);
   t.Bt = cv.take<float>((size_t)d * d);
   t.large = take_large(cv, n, d);
-  t.bstatus = cv.take<int32_t>(1);
+  t.bstatus = cv.take<int32_t>(kJitterAttempts + 1);
+  t.bscr = cv.take<double>(blocked_scratch_doubles(d));
   if (b) *b = t;
   return cv.bytes();
 }
@@ -153,6 +164,7 @@ struct Handle {
   CovPlan nplan;
   LargeScratch nlarge;
   int32_t* nbstatus;
+  double* nbscr;
   // host mirrors
   void* pinned;  // two state copies
   hipEvent_t ev[2];
@@ -254,7 +266,7 @@ int enqueue_reweight(Handle* h) {
   fa.tau_out = &b.st->tau;
   fa.err_out = &b.st->err;
   fa.done = &b.st->done;
-  fa.bstatus = b.bstatus;
+  set_blocked(fa, b.bstatus, b.bscr, h->d);
   launch_factor(fa, h->stream);
   return hip_check("smc_reweight_resample");
 }
@@ -330,10 +342,12 @@ size_t ns_carve(const phi4_ns_config& c, void* ws, Handle* h) {
   double* A = cv.take<double>((size_t)d * d);
   float* Bt = cv.take<float>((size_t)d * d);
   const LargeScratch large = take_large(cv, k, d);
-  int32_t* bstatus = cv.take<int32_t>(1);
+  int32_t* bstatus = cv.take<int32_t>(kJitterAttempts + 1);
+  double* bscr = cv.take<double>(blocked_scratch_doubles(d));
   if (h) {
     h->nlarge = large;
     h->nbstatus = bstatus;
+    h->nbscr = bscr;
     h->nst = st;
     h->absM = absM;
     h->dead = dead;
@@ -391,6 +405,7 @@ struct StepBufs {
   double* A;
   double* tau;
   LargeScratch large;
+  double* bscr;
 };
 
 size_t step_carve(int n, int d, void* ws, StepBufs* b) {
@@ -398,7 +413,7 @@ size_t step_carve(int n, int d, void* ws, StepBufs* b) {
   StepBufs t;
   t.cdf = cv.take<unsigned long long>(n > 0 ? n : 1);
   t.marks = cv.take<int32_t>(n > 0 ? n : 1);
-  t.status = cv.take<int32_t>(4);
+  t.status = cv.take<int32_t>(kJitterAttempts + 2);
   t.out = cv.take<double>(8);
   const int dd = d > 0 ? d : 1;
   t.part = cv.take<float>(cov_partial_floats(cov_plan(n > 1 ? n : 2, dd)));
@@ -406,6 +421,7 @@ size_t step_carve(int n, int d, void* ws, StepBufs* b) {
   t.A = cv.take<double>((size_t)dd * dd);
   t.tau = cv.take<double>(1);
   t.large = take_large(cv, n, dd);
+  t.bscr = cv.take<double>(blocked_scratch_doubles(dd));
   if (b) *b = t;
   return cv.bytes();
 }
@@ -629,7 +645,7 @@ int ns_step(void* handle, int32_t* done_host) {
   fa.tau_out = &h->nst->tau;
   fa.err_out = &h->nst->err;
   fa.done = &h->nst->done;
-  fa.bstatus = h->nbstatus;
+  set_blocked(fa, h->nbstatus, h->nbscr, h->d);
   launch_factor(fa, h->stream);
   MutateArgs m = {};
   m.src = h->phi;
@@ -897,7 +913,7 @@ int phi4_cholesky(const double* sigma, int32_t d, double* L, double* tau_host, v
   fa.A = L;
   fa.tau_out = b.tau;
   fa.err_out = b.status;
-  fa.bstatus = b.status + 1;
+  set_blocked(fa, b.status + 1, b.bscr, d);
   launch_factor(fa, s);
   int rc = hip_check("phi4_cholesky");
   if (rc) return rc;

@@ -382,8 +382,18 @@ struct FactorArgs {
   int32_t* err_out;
   const int32_t* done;
   int32_t cov_only;        // stop after writing sigma_out
-  int32_t* bstatus;        // scratch int of the blocked factor (d > 64): 1 = pivot failed
+  int32_t* bstatus;        // blocked factor (d > 64): kJitterAttempts + 1 ints of status
+  double* Aspec;           // blocked factor: matrices of attempts 1 .. attempts-1, then
+  double* Winv;            //   attempts inverses of 64 x 64 diagonal blocks
+  int32_t attempts;        // jitter attempts run side by side (blocked_attempts(d))
 };
+// Jitter attempts of the factorisation (tau0, then five times x100).
+constexpr int kJitterAttempts = 6;
+// Attempts the blocked factor runs side by side at size d (0 for d <= 64),
+// and the float64 scratch it needs besides A: blocked_scratch_doubles(d),
+// to be split as Aspec = base, Winv = base + (attempts - 1) d d.
+int blocked_attempts(int d);
+size_t blocked_scratch_doubles(int d);
 void launch_factor(const FactorArgs& a, hipStream_t s);
 
 // k_ns.hip

@@ -248,9 +248,10 @@ __device__ bool chol_full(double* __restrict__ A, int d, double (*D)[kTile + 1],
 
 __global__ __launch_bounds__(kFT) void factor_kernel(FactorArgs a) {
   if (a.done && *a.done) return;
-  // behind the blocked factor this kernel only runs the jitter escalation
-  // after a failed first attempt
-  if (a.bstatus && *a.bstatus == 0) return;
+  // behind the blocked factor this kernel only continues the jitter
+  // escalation after every attempt that ran there failed
+  if (a.bstatus && a.bstatus[kJitterAttempts] == 0) return;
+  const int first = a.bstatus ? a.attempts : 0;
   __shared__ double D[kTile][kTile + 1];
   __shared__ double P[kPanelRows][kTile + 1];
   __shared__ double shd[kFT / 64];
@@ -268,9 +269,10 @@ __global__ __launch_bounds__(kFT) void factor_kernel(FactorArgs a) {
   for (int i = threadIdx.x; i < d; i += kFT) tr += sig[(size_t)i * d + i];
   tr = block_reduce<kSum, 16>(tr, shd);
   double tau = 1e-10 * tr / d;
+  for (int q = 0; q < first; ++q) tau *= 100.0;
   bool ok = false;
-  for (int attempt = 0; attempt < 6 && !ok; ++attempt) {
-    if (attempt) tau *= 100.0;
+  for (int attempt = first; attempt < kJitterAttempts && !ok; ++attempt) {
+    if (attempt > first) tau *= 100.0;
     for (int e = threadIdx.x; e < d * d; e += kFT) {
       const int i = e / d, j = e % d;
       a.A[e] = sig[e] + (i == j ? tau : 0.0);
@@ -546,49 +548,71 @@ __global__ __launch_bounds__(kCF) void cov_factor_kernel(FactorArgs a) {
 
 // ------------------------------------------------------ blocked factor
 //
-// For d > 64: right-looking Cholesky of Sigma + tau0 I in 64-column panels,
-// one kernel per stage so that every stage uses as many workgroups as it
-// has independent work: the 64 x 64 diagonal block on one workgroup
-// (chol_lds), the panel below it by rows (X L11^T = A21, one lane per row),
-// and the rank-64 update of the trailing lower tiles on FP64 MFMA.  A pivot
-// failure sets bstatus; later stages then return at once and the
-// single-workgroup factor_kernel runs the full jitter escalation from
-// tau0 (so the result follows the same rule as the first attempt).
+// For d > 64: right-looking Cholesky of Sigma + tau_j I in 64-column panels,
+// one kernel per stage so that every stage uses as many workgroups as it has
+// independent work: the 64 x 64 diagonal block on one workgroup (chol_lds,
+// which also forms the block's inverse), the panel below it as the product
+// A21 L11^-T on FP64 MFMA, and the rank-64 update of the trailing lower tiles
+// on FP64 MFMA.  The jitter attempts tau_j = tau0 100^j (j < attempts) run
+// side by side in gridDim.y, each on its own copy of the matrix: the
+// sequence of attempts is decided by data the host never sees, and running
+// them together costs one factorisation's latency instead of up to six.  A
+// pivot failure sets that attempt's status and its later stages return at
+// once; the emit stage takes the first attempt that succeeded, as the
+// sequential rule would.  If every attempt fails and fewer than six ran, the
+// single-workgroup factor_kernel continues the escalation.
 
-constexpr int kBT = 256;   // threads of the row-parallel stages
+constexpr int kBT = 256;   // threads of the panel and update stages
+
+__device__ inline double* attempt_matrix(double* A, double* Aspec, int j, int d) {
+  return j == 0 ? A : Aspec + (size_t)(j - 1) * d * d;
+}
 
 __global__ __launch_bounds__(1024) void bf_init_kernel(const double* __restrict__ src, int d,
                                                        double* __restrict__ tau,
                                                        int32_t* __restrict__ status,
+                                                       int attempts,
                                                        const int32_t* __restrict__ done) {
   if (done && *done) return;
   __shared__ double shd[16];
   double t = 0.0;
   for (int i = threadIdx.x; i < d; i += 1024) t += src[(size_t)i * d + i];
   t = block_reduce<kSum, 16>(t, shd);
-  if (threadIdx.x == 0) {
-    *tau = 1e-10 * t / d;
-    *status = 0;
-  }
+  if (threadIdx.x == 0) *tau = 1e-10 * t / d;
+  if (threadIdx.x < attempts) status[threadIdx.x] = 0;
+  if (threadIdx.x == 0) status[kJitterAttempts] = 1;   // cleared by a successful emit
 }
 
-// A (lower part) = src + tau I
+__device__ inline double attempt_tau(double tau0, int j) {
+  double t = tau0;
+  for (int q = 0; q < j; ++q) t *= 100.0;
+  return t;
+}
+
+// A_j (lower part) = src + tau_j I
 __global__ __launch_bounds__(256) void bf_copy_kernel(const double* __restrict__ src,
-                                                      double* __restrict__ A, int d,
+                                                      double* __restrict__ A,
+                                                      double* __restrict__ Aspec, int d,
                                                       const double* __restrict__ tau,
                                                       const int32_t* __restrict__ done) {
   if (done && *done) return;
   const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
   if (e >= (long long)d * d) return;
+  double* Aj = attempt_matrix(A, Aspec, blockIdx.y, d);
   const int i = (int)(e / d), j = (int)(e - (long long)i * d);
-  if (j <= i) A[e] = src[e] + (i == j ? *tau : 0.0);
+  if (j <= i) Aj[e] = src[e] + (i == j ? attempt_tau(*tau, blockIdx.y) : 0.0);
 }
 
-// Diagonal block kb: factor in LDS (padded with the identity past d).
-__global__ __launch_bounds__(kCF) void bf_diag_kernel(double* __restrict__ A, int d, int kb,
+// Diagonal block kb: factor in LDS (padded with the identity past d), and,
+// when rows remain below it, the inverse W = L11^-1 for the panel stage.
+__global__ __launch_bounds__(kCF) void bf_diag_kernel(double* __restrict__ A,
+                                                      double* __restrict__ Aspec,
+                                                      double* __restrict__ Winv, int d, int kb,
                                                       int32_t* __restrict__ status,
                                                       const int32_t* __restrict__ done) {
-  if ((done && *done) || *status) return;
+  const int at = blockIdx.y;
+  if ((done && *done) || status[at]) return;
+  double* Aj = attempt_matrix(A, Aspec, at, d);
   __shared__ double M[64][65];
   __shared__ double col[64];
   __shared__ double rs[64];
@@ -597,52 +621,87 @@ __global__ __launch_bounds__(kCF) void bf_diag_kernel(double* __restrict__ A, in
   for (int e = threadIdx.x; e < 64 * 64; e += kCF) {
     const int r = e >> 6, c = e & 63;
     double v = r == c ? 1.0 : 0.0;
-    if (r < nb && c <= r) v = A[(size_t)(kb + r) * d + kb + c];
+    if (r < nb && c <= r) v = Aj[(size_t)(kb + r) * d + kb + c];
     M[r][c] = v;
   }
   __syncthreads();
   if (!chol_lds<64>(M, col, rs, &flag)) {
-    if (threadIdx.x == 0) *status = 1;
+    if (threadIdx.x == 0) status[at] = 1;
     return;
   }
   for (int e = threadIdx.x; e < 64 * 64; e += kCF) {
     const int r = e >> 6, c = e & 63;
-    if (r < nb && c <= r) A[(size_t)(kb + r) * d + kb + c] = M[r][c];
+    if (r < nb && c <= r) Aj[(size_t)(kb + r) * d + kb + c] = M[r][c];
+  }
+  if (kb + 64 >= d || threadIdx.x >= 64) return;
+  // forward substitution L w = e_c, one column per lane (w[k] = 0 for k < c)
+  const int c = threadIdx.x;
+  double* W = Winv + (size_t)at * 4096;
+  double w[64];
+#pragma unroll
+  for (int i = 0; i < 64; ++i) {
+    double t = i == c ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < i; ++k) t = fma(-M[i][k], w[k], t);
+    w[i] = i >= c ? t / M[i][i] : 0.0;
+    W[i * 64 + c] = w[i];
   }
 }
 
-// Panel below block kb: row i (one lane) solves x L11^T = a, column by
-// column; L11 entries are uniform over the wave (scalar loads).
+// Panel below block kb: X = A21 L11^-T = A21 W^T on FP64 MFMA, 64 rows per
+// workgroup; wave v computes rows 16v..16v+15 as four 16 x 16 tiles.
 __global__ __launch_bounds__(kBT) void bf_trsm_kernel(double* __restrict__ A,
-                                                      const double* __restrict__ L11, int d,
+                                                      double* __restrict__ Aspec,
+                                                      const double* __restrict__ Winv, int d,
                                                       int kb, const int32_t* __restrict__ status,
                                                       const int32_t* __restrict__ done) {
-  if ((done && *done) || *status) return;
-  const int i = kb + 64 + blockIdx.x * kBT + threadIdx.x;
-  const int ic = min(i, d - 1);                 // valid row, masked on the write
-  double x[64];
-#pragma unroll
-  for (int m = 0; m < 64; ++m) x[m] = A[(size_t)ic * d + kb + m];
-#pragma unroll
-  for (int m = 0; m < 64; ++m) {
-    const double* Lm = L11 + (size_t)(kb + m) * d + kb;   // row m of L11
-    x[m] = x[m] / Lm[m];
-#pragma unroll
-    for (int j = m + 1; j < 64; ++j) x[j] = fma(-x[m], L11[(size_t)(kb + j) * d + kb + m], x[j]);
+  const int at = blockIdx.y;
+  if ((done && *done) || status[at]) return;
+  double* Aj = attempt_matrix(A, Aspec, at, d);
+  const double* W = Winv + (size_t)at * 4096;
+  __shared__ double Xs[64][65];
+  __shared__ double Ws[64][65];
+  const int r0 = kb + 64 + blockIdx.x * 64;
+  for (int e = threadIdx.x; e < 64 * 64; e += kBT) {
+    const int r = e >> 6, c = e & 63;
+    const double v = Aj[(size_t)min(r0 + r, d - 1) * d + kb + c];
+    Xs[r][c] = r0 + r < d ? v : 0.0;
+    Ws[r][c] = W[e];
   }
-  if (i < d) {
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int pl = lane & 15, gl = lane >> 4;
+  f64x4 acc[4];
 #pragma unroll
-    for (int m = 0; m < 64; ++m) A[(size_t)i * d + kb + m] = x[m];
+  for (int b = 0; b < 4; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) {
+    const double av = Xs[16 * wv + pl][4 * kk + gl];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const double bv = Ws[16 * b + pl][4 * kk + gl];   // W^T[k][col] = W[col][k]
+      acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[b], 0, 0, 0);
+    }
   }
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = r0 + 16 * wv + gl + 4 * r;
+      if (row < d) Aj[(size_t)row * d + kb + 16 * b + pl] = acc[b][r];
+    }
 }
 
 // Trailing update A[I][J] -= X_I X_J^T for the 64 x 64 tiles (I, J), J <= I,
 // below block kb; X is the solved panel.  Wave w computes a 32 x 32 quarter
 // as 2 x 2 FP64 MFMA tiles (K = 4 per instruction).
-__global__ __launch_bounds__(256) void bf_syrk_kernel(double* __restrict__ A, int d, int kb,
+__global__ __launch_bounds__(256) void bf_syrk_kernel(double* __restrict__ A,
+                                                      double* __restrict__ Aspec, int d, int kb,
                                                       const int32_t* __restrict__ status,
                                                       const int32_t* __restrict__ done) {
-  if ((done && *done) || *status) return;
+  const int at = blockIdx.y;
+  if ((done && *done) || status[at]) return;
+  double* Aj = attempt_matrix(A, Aspec, at, d);
   __shared__ double Xi[64][65];
   __shared__ double Xj[64][65];
   int I = 0, J = blockIdx.x;
@@ -652,7 +711,7 @@ __global__ __launch_bounds__(256) void bf_syrk_kernel(double* __restrict__ A, in
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
     const int r = e >> 6, c = e & 63;
     const int ri = min(r0 + r, d - 1), rj = min(s0 + r, d - 1);
-    const double vi = A[(size_t)ri * d + kb + c], vj = A[(size_t)rj * d + kb + c];
+    const double vi = Aj[(size_t)ri * d + kb + c], vj = Aj[(size_t)rj * d + kb + c];
     Xi[r][c] = r0 + r < d ? vi : 0.0;
     Xj[r][c] = s0 + r < d ? vj : 0.0;
   }
@@ -668,7 +727,7 @@ __global__ __launch_bounds__(256) void bf_syrk_kernel(double* __restrict__ A, in
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = r0 + 32 * wr + 16 * a + gl + 4 * r, c = s0 + 32 * wc + 16 * b + pl;
-        acc[a][b][r] = A[(size_t)min(row, d - 1) * d + min(c, d - 1)];
+        acc[a][b][r] = Aj[(size_t)min(row, d - 1) * d + min(c, d - 1)];
       }
 #pragma unroll
   for (int kk = 0; kk < 16; ++kk)
@@ -687,25 +746,48 @@ __global__ __launch_bounds__(256) void bf_syrk_kernel(double* __restrict__ A, in
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = r0 + 32 * wr + 16 * a + gl + 4 * r, c = s0 + 32 * wc + 16 * b + pl;
-        if (row < d && c < d && c <= row) A[(size_t)row * d + c] = acc[a][b][r];
+        if (row < d && c < d && c <= row) Aj[(size_t)row * d + c] = acc[a][b][r];
       }
 }
 
-// Outputs of a successful blocked factor: the upper part of A zeroed and
-// Bt[k][c] = eps L[c][k] in float32.
-__global__ __launch_bounds__(256) void bf_emit_kernel(double* __restrict__ A, int d,
+// Outputs from the first attempt that succeeded: its factor copied into A
+// with the upper part zeroed, Bt[k][c] = eps L[c][k] in float32, and tau.
+__global__ __launch_bounds__(256) void bf_emit_kernel(double* __restrict__ A,
+                                                      double* __restrict__ Aspec, int d,
                                                       float* __restrict__ Bt, int ldb,
                                                       const double* __restrict__ eps_ptr,
-                                                      const int32_t* __restrict__ status,
+                                                      double* __restrict__ tau,
+                                                      int32_t* __restrict__ status, int attempts,
+                                                      int32_t* __restrict__ err_out,
                                                       const int32_t* __restrict__ done) {
-  if ((done && *done) || *status) return;
+  if (done && *done) return;
+  int j = 0;
+  while (j < attempts && status[j]) ++j;
   const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (long long)d * d) return;
-  const int i = (int)(e / d), j = (int)(e - (long long)i * d);
-  if (j > i) A[e] = 0.0;
-  if (Bt) {
-    const int k = i, c = j;   // Bt row k, column c
-    Bt[(size_t)k * ldb + c] = c >= k ? (float)(*eps_ptr * A[(size_t)c * d + k]) : 0.f;
+  if (j == attempts) {
+    // no attempt succeeded: the escalation ends here after six attempts,
+    // else the single-workgroup kernel continues it
+    if (e == 0) {
+      if (attempts >= kJitterAttempts) {
+        status[kJitterAttempts] = 0;
+        if (err_out) *err_out = PHI4_ECHOL;
+      }
+    }
+    return;
+  }
+  const double* Aj = attempt_matrix(A, Aspec, j, d);
+  if (e < (long long)d * d) {
+    const int i = (int)(e / d), c = (int)(e - (long long)i * d);
+    if (j > 0 || c > i) A[e] = c <= i ? Aj[e] : 0.0;
+    if (Bt) {
+      const int k = i;   // Bt row k, column c
+      Bt[(size_t)k * ldb + c] = c >= k ? (float)(*eps_ptr * Aj[(size_t)c * d + k]) : 0.f;
+    }
+  }
+  // block 0 alone touches tau and the summary word (no block reads either)
+  if (e == 0) {
+    *tau = attempt_tau(*tau, j);
+    status[kJitterAttempts] = 0;
   }
 }
 
@@ -730,6 +812,17 @@ CovPlan cov_plan(int n, int d) {
   p.chunks = (n + p.chunk - 1) / p.chunk;
   if (p.chunks < 1) p.chunks = 1;
   return p;
+}
+
+int blocked_attempts(int d) {
+  if (d <= kSmallD) return 0;
+  return d <= 2048 ? kJitterAttempts : 3;
+}
+
+size_t blocked_scratch_doubles(int d) {
+  const int P = blocked_attempts(d);
+  if (P == 0) return 0;
+  return (size_t)(P - 1) * d * d + (size_t)P * 4096;
 }
 
 size_t cov_partial_floats(const CovPlan& p) {
@@ -765,22 +858,26 @@ void launch_factor(const FactorArgs& a, hipStream_t s) {
   }
   if (a.cov_only) return;
   if (a.bstatus && d > kSmallD) {
-    // blocked factor at tau0; the single-workgroup kernel below only runs
-    // if one of its pivots failed
+    // blocked factor, the jitter attempts side by side; the single-workgroup
+    // kernel below only runs if all of them failed and fewer than six ran
+    const int P = a.attempts;
     const double* src = a.sigma_in ? a.sigma_in : a.sigma_out;
     const unsigned nel = (unsigned)(((long long)d * d + 255) / 256);
-    bf_init_kernel<<<1, 1024, 0, s>>>(src, d, a.tau_out, a.bstatus, a.done);
-    bf_copy_kernel<<<nel, 256, 0, s>>>(src, a.A, d, a.tau_out, a.done);
+    bf_init_kernel<<<1, 1024, 0, s>>>(src, d, a.tau_out, a.bstatus, P, a.done);
+    bf_copy_kernel<<<dim3(nel, P), 256, 0, s>>>(src, a.A, a.Aspec, d, a.tau_out, a.done);
     for (int kb = 0; kb < d; kb += 64) {
-      bf_diag_kernel<<<1, kCF, 0, s>>>(a.A, d, kb, a.bstatus, a.done);
+      bf_diag_kernel<<<dim3(1, P), kCF, 0, s>>>(a.A, a.Aspec, a.Winv, d, kb, a.bstatus, a.done);
       const int below = d - kb - 64;
       if (below > 0) {
-        bf_trsm_kernel<<<(below + kBT - 1) / kBT, kBT, 0, s>>>(a.A, a.A, d, kb, a.bstatus, a.done);
         const int nt = (below + 63) / 64;
-        bf_syrk_kernel<<<nt * (nt + 1) / 2, 256, 0, s>>>(a.A, d, kb, a.bstatus, a.done);
+        bf_trsm_kernel<<<dim3(nt, P), kBT, 0, s>>>(a.A, a.Aspec, a.Winv, d, kb, a.bstatus,
+                                                   a.done);
+        bf_syrk_kernel<<<dim3(nt * (nt + 1) / 2, P), 256, 0, s>>>(a.A, a.Aspec, d, kb,
+                                                                  a.bstatus, a.done);
       }
     }
-    bf_emit_kernel<<<nel, 256, 0, s>>>(a.A, d, a.Bt, a.ldb, a.eps_ptr, a.bstatus, a.done);
+    bf_emit_kernel<<<nel, 256, 0, s>>>(a.A, a.Aspec, d, a.Bt, a.ldb, a.eps_ptr, a.tau_out,
+                                       a.bstatus, P, a.err_out, a.done);
   }
   factor_kernel<<<1, kFT, 0, s>>>(a);
 }
