@@ -47,6 +47,11 @@ def parse():
     ap.add_argument("--no-bf16", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the free-theory check and the L=16 SMC / L=32 NS workloads")
+    ap.add_argument("--batch-levels", type=int, default=3,
+                    help="levels of the 64-run batched workload (0: skip it; large values "
+                         "run every run to beta = 1)")
+    ap.add_argument("--only-extra", action="store_true",
+                    help="run only the extra workloads and print them (profiling aid)")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MIB",
                     help="only copy MIB mebibytes device-to-device with torch and exit "
                          "(calibrates the HBM byte counters of a profiler run)")
@@ -155,9 +160,55 @@ def ns_workload(P, torch, L, n, k, n_steps, precision, iters, warm=2, seed=0):
     return out
 
 
+def batch_workload(P, torch, max_levels, n=8192, n_steps=20):
+    """64 independent SMC runs advanced together: L = (8, 16, 32, 64)[r mod 4],
+    (m2, lambda) = grid[(r div 4) mod 6] over m2 in (-4, -2, -1) x lambda in
+    (4, 8), float32 proposal products for runs 0-23 and 48-63, bfloat16 for
+    24-47; N = 8192 each, Philox key (seed 0, run r)."""
+    grid = [(m2, lam) for m2 in (-4.0, -2.0, -1.0) for lam in (4.0, 8.0)]
+    cfg = []
+    for r in range(64):
+        m2, lam = grid[(r // 4) % 6]
+        cfg.append(((8, 16, 32, 64)[r % 4], m2, lam, "fp32" if (r // 24) % 2 == 0 else "bf16"))
+    # time the proposal-product tiles of the large shapes outside the timed region
+    for L in (32, 64):
+        for prec in ("fp32", "bf16"):
+            t = P.SMC(L, n, -4.0, 8.0, ess_frac=0.5, n_steps=1, seed=1, precision=prec)
+            P.smc_reweight_resample(t.h)
+            P.smc_mutate(t.h)
+            t.close()
+    progress("batch: tiles timed")
+    runs = [P.SMC(L, n, m2, lam, ess_frac=0.5, n_steps=n_steps, seed=0, run=r, precision=prec)
+            for r, (L, m2, lam, prec) in enumerate(cfg)]
+    progress("batch: 64 runs initialised")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, levels = P.smc_batch_run([s.h for s in runs], max_levels=max_levels)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pu = sum(levels) * n * n_steps
+    su = sum(lv * n * n_steps * L * L for lv, (L, _, _, _) in zip(levels, cfg))
+    per_run = []
+    for s, lv, (L, m2, lam, prec) in zip(runs, levels, cfg):
+        per_run.append(dict(L=L, m2=m2, lam=lam, precision=prec, levels=lv,
+                            beta=s.observables()["beta_or_logX"], logz=s.logz(),
+                            mean_abs_m=s.observables()["mean_abs_m"]))
+        s.close()
+    tiles = {f"L{L}_{prec}": P.phi4_tile_choice(n, L * L, prec)
+             for L in (32, 64) for prec in ("fp32", "bf16")}
+    return dict(value=pu / wall, site_updates_per_s=su / wall, wall_s=wall,
+                all_finished=rc == P.PHI4_DONE, max_levels=max_levels, n=n, n_steps=n_steps,
+                gemm_tile_rows=tiles, runs=per_run)
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def extra_workloads(P, torch):
     """Free-theory check of the main workload, SMC at L = 16 and NS at L = 32."""
     ex = {}
+    progress("free-theory check")
     fz = smc_workload(P, torch, 8, 4096, 1.0, 0.0, 20, "fp32")
     exact = free_log_z(8, 1.0)
     ex["free_theory_L8"] = dict(logz=fz["logz"], exact=exact, dlogz=fz["logz"] - exact,
@@ -167,8 +218,10 @@ def extra_workloads(P, torch):
         for prec in ("fp32", "bf16"):
             ex[f"smc_L16_N16384_lam{lam:g}_{prec}"] = smc_workload(P, torch, 16, 16384, -4.0, lam,
                                                                      20, prec)
+            progress(f"SMC L=16 lambda={lam:g} {prec} done")
     for prec in ("fp32", "bf16"):
         ex[f"ns_L32_n4096_k2048_{prec}"] = ns_workload(P, torch, 32, 4096, 2048, 40, prec, 8)
+        progress(f"NS L=32 {prec} done")
     return ex
 
 
@@ -198,6 +251,12 @@ def main():
         sys.exit(1)
     if args.copy_probe > 0:
         copy_probe(torch, args.copy_probe)
+        return
+    if args.only_extra:
+        ex = extra_workloads(P, torch)
+        if args.batch_levels > 0:
+            ex["batch64"] = batch_workload(P, torch, args.batch_levels)
+        print(json.dumps({"workloads": ex}), flush=True)
         return
     w = WORKLOAD
     d = w["L"] ** 2
@@ -240,6 +299,8 @@ def main():
                         "mutate_kernel_us": rb["kernel_ms"] / max(rb["launches"], 1) * 1e3}
     if not args.no_extra and args.precision == "fp32":
         line["workloads"] = extra_workloads(P, torch)
+        if args.batch_levels > 0:
+            line["workloads"]["batch64"] = batch_workload(P, torch, args.batch_levels)
     if not args.no_cpu_baseline:
         cb = cpu_baseline()
         line["dlogz_vs_oracle_seed0"] = abs(r["logz_seed0"] - cb.pop("logz"))

@@ -145,6 +145,27 @@ int smc_mutate(void* handle, double* acc_host);
  * (optional) receives the number of levels. */
 int smc_run(void* handle, int32_t max_levels, int32_t* levels_host);
 
+/* Batched form (Sec. 2 tempered SMC, many independent runs): advances the
+ * n_runs SMC handles together until every run has finished its sweep at
+ * beta = 1 or max_levels levels have run (levels go in pairs after the first,
+ * so a run may take max_levels + 1).  The first level of every run is
+ * enqueued on the run's own stream; then two levels of all runs are captured
+ * into one hipGraph (independent runs on separate branches, parameters read
+ * from device memory, finished runs' kernels return at once) and the graph
+ * is replayed on a private stream, with the runs' levels, beta and errors
+ * gathered into one status read after each replay.  `stream` is the caller's
+ * stream: it and the runs' streams are synchronised before the first level,
+ * and the call returns with all work complete.  The runs' shapes, couplings and
+ * precisions may all differ; each handle keeps its own buffers.  On return
+ * the particles of every run are in its phi / S, levels_host[r] (may be
+ * NULL) holds run r's level count, and logz / phi4_observables report each
+ * run.  Returns PHI4_DONE when every run finished, PHI4_OK when max_levels
+ * came first, or the first device error.  Allocates a few small buffers,
+ * streams and the graph for the duration of the call; the handles must not
+ * be used concurrently by other calls. */
+int smc_batch_run(void* const* handles, int32_t n_runs, int32_t max_levels, int32_t* levels_host,
+                  void* stream);
+
 /* ------------------------------------------------------- nested sampling */
 
 size_t ns_workspace_bytes(const phi4_ns_config* cfg);
@@ -197,6 +218,14 @@ int phi4_observables(void* handle, double* out_host);
 #define PHI4_SWEEP_FUSED 1
 #define PHI4_SWEEP_PASSES 2
 int phi4_set_sweep(void* handle, int32_t form);
+
+/* Tile of the three-pass proposal product (autotuned).  The first sweep of a
+ * shape (n particles, d sites, precision) on a device times each particle-tile
+ * height (32, 64, 128 rows by 64 columns) on the caller's stream and keeps the
+ * fastest for the process.  *rows_host receives the height chosen for the
+ * current device, or 0 if that shape has not run yet.  Host-only, never
+ * fails for valid pointers. */
+int phi4_tile_choice(int32_t n, int32_t d, int32_t precision, int32_t* rows_host);
 
 /* Kernel timing: while enabled, every mutation launch of
  * smc_mutate / smc_run / ns_step is bracketed by HIP events on the handle's

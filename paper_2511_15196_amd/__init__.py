@@ -91,6 +91,18 @@ def smc_run(h, max_levels=100000):
     return rc, levels.value
 
 
+def smc_batch_run(handles, max_levels=100000, stream=None):
+    """Advance many SMC handles together (one replayed hipGraph per pair of
+    levels); returns (rc, levels per run)."""
+    n = len(handles)
+    arr = (ctypes.c_void_p * n)(*[h.value if isinstance(h, ctypes.c_void_p) else h
+                                  for h in handles])
+    levels = (ctypes.c_int32 * n)()
+    rc = _check(lib().smc_batch_run(arr, ctypes.c_int32(n), ctypes.c_int32(max_levels), levels,
+                                    _stream(stream)), "smc_batch_run")
+    return rc, list(levels)
+
+
 def ns_workspace_bytes(cfg):
     return int(lib().ns_workspace_bytes(ctypes.byref(cfg)))
 
@@ -127,6 +139,13 @@ def phi4_observables(h):
 
 
 SWEEPS = {"auto": 0, "fused": 1, "passes": 2}
+
+
+def phi4_tile_choice(n, d, precision="fp32"):
+    rows = ctypes.c_int32(0)
+    _check(lib().phi4_tile_choice(n, d, PRECISIONS[precision], ctypes.byref(rows)),
+           "phi4_tile_choice")
+    return rows.value
 
 
 def phi4_set_sweep(h, form="auto"):

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <algorithm>
 #include <string>
 #include <utility>
 #include <vector>
@@ -57,9 +58,9 @@ double default_eps0(int d, double eps0) { return eps0 > 0 ? eps0 : 2.38 / std::s
 
 // Scratch of the three-pass sweep for n particles.
 LargeScratch take_large(Carver& cv, int n, int d) {
-  if (n <= 0) return LargeScratch{nullptr, nullptr, nullptr};
+  if (n <= 0) return LargeScratch{nullptr, nullptr, nullptr, nullptr};
   void* base = cv.take<char>(large_scratch_bytes(n, d));
-  return cv.base ? large_scratch(base, n, d) : LargeScratch{nullptr, nullptr, nullptr};
+  return cv.base ? large_scratch(base, n, d) : LargeScratch{nullptr, nullptr, nullptr, nullptr};
 }
 
 // ------------------------------------------------------------------ SMC
@@ -435,6 +436,36 @@ bool ws_ok(void* ws, size_t have, size_t need, std::string* why) {
 
 }  // namespace
 
+namespace {
+
+// Resources of one batched call, released on every exit path.
+struct BatchRes {
+  std::vector<hipStream_t> branches;
+  std::vector<hipEvent_t> events;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const SmcState** dptrs = nullptr;
+  BatchStatus* dstat = nullptr;
+  BatchStatus* hstat = nullptr;
+  std::vector<std::pair<Handle*, hipStream_t>> saved_streams;
+  std::vector<std::pair<Handle*, bool>> saved_timing;
+  ~BatchRes() {
+    for (auto& p : saved_streams) p.first->stream = p.second;
+    for (auto& p : saved_timing) p.first->timing = p.second;
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    for (hipStream_t st : branches) (void)hipStreamDestroy(st);
+    if (dptrs) (void)hipFree(dptrs);
+    if (dstat) (void)hipFree(dstat);
+    if (hstat) (void)hipHostFree(hstat);
+  }
+};
+
+constexpr int kBatchBranches = 4;
+
+}  // namespace
+
 extern "C" {
 
 const char* phi4_last_error(void) { return g_err.c_str(); }
@@ -574,6 +605,156 @@ int smc_run(void* handle, int32_t max_levels, int32_t* levels_host) {
   if (s.err) return state_error(s.err);
   if (levels_host) *levels_host = s.level;
   return s.beta >= 1.0 ? PHI4_DONE : PHI4_OK;
+}
+
+// ------------------------------------------------------------------ batch
+
+
+int smc_batch_run(void* const* handles, int32_t n_runs, int32_t max_levels, int32_t* levels_host,
+                  void* stream) {
+  if (!handles || n_runs < 1) return fail(PHI4_EINVAL, "smc_batch_run: need n_runs >= 1 handles");
+  if (max_levels < 1) return fail(PHI4_EINVAL, "smc_batch_run: max_levels must be >= 1");
+  std::vector<Handle*> hs((size_t)n_runs);
+  for (int r = 0; r < n_runs; ++r) {
+    hs[r] = as_handle(handles[r], 0);
+    if (!hs[r]) return fail(PHI4_EINVAL, "smc_batch_run: handle " + std::to_string(r) +
+                                             " is not an SMC handle");
+    for (int q = 0; q < r; ++q)
+      if (hs[q] == hs[r]) return fail(PHI4_EINVAL, "smc_batch_run: a handle appears twice");
+  }
+  hipStream_t caller = static_cast<hipStream_t>(stream);
+  BatchRes res;
+  // Level 1 of every run outside the graph, on the run's own stream: it
+  // also settles pending ancestors and times the proposal-product tiles of
+  // each shape (nothing can be timed during a capture).
+  for (Handle* h : hs) {
+    int rc = enqueue_reweight(h);
+    if (!rc) rc = enqueue_mutate(h);
+    if (rc) return rc;
+  }
+  for (Handle* h : hs) HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(hipStreamSynchronize(caller));
+  // capture and replay on a private stream (the caller's may be the legacy
+  // null stream, which cannot be captured)
+  hipStream_t origin = nullptr;
+  HIP_TRY(hipStreamCreateWithFlags(&origin, hipStreamNonBlocking));
+  res.branches.push_back(origin);
+
+  HIP_TRY(hipMalloc(&res.dptrs, sizeof(SmcState*) * (size_t)n_runs));
+  HIP_TRY(hipMalloc(&res.dstat, sizeof(BatchStatus) * (size_t)n_runs));
+  HIP_TRY(hipHostMalloc(&res.hstat, sizeof(BatchStatus) * (size_t)n_runs, hipHostMallocDefault));
+  {
+    std::vector<const SmcState*> ptrs((size_t)n_runs);
+    for (int r = 0; r < n_runs; ++r) ptrs[r] = hs[r]->sb.st;
+    HIP_TRY(hipMemcpy(res.dptrs, ptrs.data(), sizeof(SmcState*) * (size_t)n_runs,
+                      hipMemcpyHostToDevice));
+  }
+  const int nb = std::min(kBatchBranches, n_runs);
+  std::vector<hipStream_t> br;
+  for (int k = 0; k < nb; ++k) {
+    hipStream_t st = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    res.branches.push_back(st);
+    br.push_back(st);
+  }
+  for (int k = 0; k < nb + 1; ++k) {
+    hipEvent_t e = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    res.events.push_back(e);
+  }
+  // branches balanced by the work of one sweep (largest first)
+  std::vector<int> order((size_t)n_runs);
+  for (int r = 0; r < n_runs; ++r) order[r] = r;
+  auto cost = [&](int r) {
+    const double d = hs[r]->d;
+    return (double)hs[r]->n * d * (d + 16.0) * std::max(hs[r]->n_steps, 1);
+  };
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  std::vector<double> load((size_t)nb, 0.0);
+  std::vector<int> branch_of((size_t)n_runs);
+  for (int r : order) {
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    branch_of[r] = k;
+    load[k] += cost(r);
+  }
+  // Two levels of every run per replay: each level flips the particle
+  // buffers, so the captured pointers are valid for every replay; a run
+  // that has finished makes its kernels return at once.
+  for (Handle* h : hs) {
+    res.saved_streams.push_back({h, h->stream});
+    res.saved_timing.push_back({h, h->timing});
+    h->timing = false;
+  }
+  // host-side buffer parity of every run; two captured levels leave it as
+  // it was, and a capture that fails part-way must not change it either
+  std::vector<std::pair<int, bool>> parity;
+  for (Handle* h : hs) parity.push_back({h->cur, h->anc_pending});
+  HIP_TRY(hipStreamBeginCapture(origin, hipStreamCaptureModeRelaxed));
+  int rc = PHI4_OK;
+  {
+    bool ok = hipEventRecord(res.events[nb], origin) == hipSuccess;
+    for (int k = 0; k < nb && ok; ++k)
+      ok = hipStreamWaitEvent(br[k], res.events[nb], 0) == hipSuccess;
+    for (int r = 0; r < n_runs && ok && !rc; ++r) {
+      Handle* h = hs[r];
+      h->stream = br[branch_of[r]];
+      for (int lv = 0; lv < 2 && !rc; ++lv) {
+        rc = enqueue_reweight(h);
+        if (!rc) rc = enqueue_mutate(h);
+      }
+    }
+    for (int k = 0; k < nb && ok; ++k) {
+      ok = hipEventRecord(res.events[k], br[k]) == hipSuccess &&
+           hipStreamWaitEvent(origin, res.events[k], 0) == hipSuccess;
+    }
+    if (ok) {
+      launch_batch_status(res.dptrs, n_runs, res.dstat, origin);
+      ok = hipMemcpyAsync(res.hstat, res.dstat, sizeof(BatchStatus) * (size_t)n_runs,
+                          hipMemcpyDeviceToHost, origin) == hipSuccess;
+    }
+    const hipError_t ec = hipStreamEndCapture(origin, &res.graph);
+    if (!rc && (!ok || ec != hipSuccess))
+      rc = fail(PHI4_EHIP, "smc_batch_run: stream capture failed");
+  }
+  for (auto& p : res.saved_streams) p.first->stream = p.second;
+  res.saved_streams.clear();
+  for (int r = 0; r < n_runs; ++r) {
+    hs[r]->cur = parity[r].first;
+    hs[r]->anc_pending = parity[r].second;
+  }
+  if (rc) return rc;
+  HIP_TRY(hipGraphInstantiate(&res.exec, res.graph, nullptr, nullptr, 0));
+  bool all_done = false;
+  int err = 0;
+  for (int lv = 1; lv < max_levels && !all_done && !err; lv += 2) {
+    HIP_TRY(hipGraphLaunch(res.exec, origin));
+    HIP_TRY(hipStreamSynchronize(origin));
+    all_done = true;
+    for (int r = 0; r < n_runs; ++r) {
+      if (res.hstat[r].err) err = res.hstat[r].err;
+      if (res.hstat[r].beta < 1.0) all_done = false;
+    }
+  }
+  if (max_levels == 1) {
+    launch_batch_status(res.dptrs, n_runs, res.dstat, origin);
+    HIP_TRY(hipMemcpyAsync(res.hstat, res.dstat, sizeof(BatchStatus) * (size_t)n_runs,
+                           hipMemcpyDeviceToHost, origin));
+    HIP_TRY(hipStreamSynchronize(origin));
+    all_done = true;
+    for (int r = 0; r < n_runs; ++r) {
+      if (res.hstat[r].err) err = res.hstat[r].err;
+      if (res.hstat[r].beta < 1.0) all_done = false;
+    }
+  }
+  for (Handle* h : hs) {
+    rc = settle(h);
+    if (rc) return rc;
+  }
+  for (Handle* h : hs) HIP_TRY(hipStreamSynchronize(h->stream));
+  if (levels_host)
+    for (int r = 0; r < n_runs; ++r) levels_host[r] = res.hstat[r].level;
+  if (err) return state_error(err);
+  return all_done ? PHI4_DONE : PHI4_OK;
 }
 
 size_t ns_workspace_bytes(const phi4_ns_config* cfg) {
@@ -750,6 +931,12 @@ int phi4_observables(void* handle, double* out) {
   out[7] = s->tau;
   out[8] = 0.0;
   out[9] = s->done;
+  return PHI4_OK;
+}
+
+int phi4_tile_choice(int32_t n, int32_t d, int32_t precision, int32_t* rows_host) {
+  if (!rows_host) return fail(PHI4_EINVAL, "phi4_tile_choice: NULL output");
+  *rows_host = large_tile_choice(n, d, precision);
   return PHI4_OK;
 }
 

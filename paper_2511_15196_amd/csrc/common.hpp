@@ -243,12 +243,14 @@ struct NsState {
 // ------------------------------------------------------ kernel interfaces
 
 // Scratch of the large-lattice sweep (k_large.hip) for n particles: normals
-// (n x large_dz(d) floats), proposals (n x d floats) and per-particle
-// acceptance counts (n int32, zero between sweeps).
+// (n x large_dz(d) floats), proposals (n x d floats), per-particle
+// acceptance counts (n int32, zero between sweeps) and the factor in the
+// operand layout of the proposal product (large_dz(d)^2 floats).
 struct LargeScratch {
   float* z;
   float* prop;
   int32_t* accp;
+  void* lp;
 };
 
 struct MutateArgs {
@@ -295,6 +297,9 @@ int large_dz(int d);
 size_t large_scratch_bytes(int n, int d);
 LargeScratch large_scratch(void* base, int n, int d);
 void launch_large_init(const LargeScratch& w, int n, hipStream_t s);
+// Particle-tile height the proposal product uses at this shape on the
+// current device once it has been timed (0 before).
+int large_tile_choice(int n, int d, int precision);
 int launch_mutate_large(const MutateArgs& a, const LargeScratch& w, int precision, hipStream_t s);
 
 // k_field.hip
@@ -418,5 +423,10 @@ void launch_smc_state_init(SmcState* st, double eps0, double acc_target, double 
                            hipStream_t s);
 void launch_ns_state_init(NsState* st, double eps0, double acc_target, hipStream_t s);
 void launch_mean_abs(const float* absM, int n, double* out, const int32_t* done, hipStream_t s);
+struct BatchStatus {
+  double beta;
+  int32_t level, done, err, pad;
+};
+void launch_batch_status(const SmcState* const* st, int runs, BatchStatus* out, hipStream_t s);
 
 }  // namespace phi4

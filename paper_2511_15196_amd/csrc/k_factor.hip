@@ -62,9 +62,10 @@ __global__ __launch_bounds__(64) void cov_partial_kernel(const float* __restrict
   const int k_begin = chunk * p.chunk, k_end = min(p.n, k_begin + p.chunk);
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
   float m1 = 0.f;
-  // 8 MFMA steps (32 particles) per batch: all loads of a batch are issued
-  // before the matrix instructions consume them
-  constexpr int kU = 8;
+  // 32 MFMA steps (128 particles) per batch: the row indices of a batch, then
+  // all its field loads, are issued before the matrix instructions consume
+  // them (two memory round trips per batch)
+  constexpr int kU = 32;
   for (int k0 = k_begin; k0 < k_end; k0 += 4 * kU) {
     int rk[kU];
 #pragma unroll
@@ -106,17 +107,21 @@ __global__ __launch_bounds__(64) void cov_partial_kernel(const float* __restrict
   old = __builtin_amdgcn_readfirstlane(old);
   if (old != p.chunks - 1) return;
   __threadfence();
+  {
+    // every partial of the block in flight at once (one round trip)
+    float x[4][kMaxChunks];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int e = lane + 64 * t;
-    float x[kMaxChunks];
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int c = 0; c < kMaxChunks; ++c)
-      x[c] = w.part[((size_t)min(c, p.chunks - 1) * p.blocks + blk) * 256 + e];
-    double m2 = 0.0;
+      for (int c = 0; c < kMaxChunks; ++c)
+        x[t][c] = w.part[((size_t)min(c, p.chunks - 1) * p.blocks + blk) * 256 + lane + 64 * t];
 #pragma unroll
-    for (int c = 0; c < kMaxChunks; ++c) m2 += c < p.chunks ? (double)x[c] : 0.0;
-    w.fin[(size_t)blk * 256 + e] = m2;
+    for (int t = 0; t < 4; ++t) {
+      double m2 = 0.0;
+#pragma unroll
+      for (int c = 0; c < kMaxChunks; ++c) m2 += c < p.chunks ? (double)x[t][c] : 0.0;
+      w.fin[(size_t)blk * 256 + lane + 64 * t] = m2;
+    }
   }
   if (bi == bj && lane < 16) {
     float x[kMaxChunks];
@@ -633,19 +638,49 @@ __global__ __launch_bounds__(kCF) void bf_diag_kernel(double* __restrict__ A,
     const int r = e >> 6, c = e & 63;
     if (r < nb && c <= r) Aj[(size_t)(kb + r) * d + kb + c] = M[r][c];
   }
-  if (kb + 64 >= d || threadIdx.x >= 64) return;
-  // forward substitution L w = e_c, one column per lane (w[k] = 0 for k < c)
-  const int c = threadIdx.x;
-  double* W = Winv + (size_t)at * 4096;
-  double w[64];
+  if (kb + 64 >= d) return;
+  // W = L^-1 by 16 x 16 blocks: the diagonal blocks W_bb = L_bb^-1 by
+  // forward substitution (lane 16 b + c owns column c of block b), then
+  // W_ij = -W_ii sum_{j <= k < i} L_ik W_kj for i > j, one block distance
+  // i - j at a time (every block it needs is then known).
+  __shared__ double Wl[64][65];
+  __shared__ double Tt[3][16][17];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * 64; e += kCF) Wl[e >> 6][e & 63] = 0.0;
+  __syncthreads();
+  if (tid < 64) {
+    const int o = 16 * (tid >> 4), c = tid & 15;
+    double w[16];
 #pragma unroll
-  for (int i = 0; i < 64; ++i) {
-    double t = i == c ? 1.0 : 0.0;
+    for (int i = 0; i < 16; ++i) {
+      double t = i == c ? 1.0 : 0.0;
 #pragma unroll
-    for (int k = 0; k < i; ++k) t = fma(-M[i][k], w[k], t);
-    w[i] = i >= c ? t / M[i][i] : 0.0;
-    W[i * 64 + c] = w[i];
+      for (int k = 0; k < i; ++k) t = fma(-M[o + i][o + k], w[k], t);
+      w[i] = i >= c ? t / M[o + i][o + i] : 0.0;
+      Wl[o + i][o + c] = w[i];
+    }
   }
+  __syncthreads();
+  for (int dist = 1; dist < 4; ++dist) {
+    const int work = (4 - dist) * 256;
+    for (int e = tid; e < work; e += kCF) {
+      const int j = e >> 8, r = (e >> 4) & 15, c = e & 15, i = j + dist;
+      double t = 0.0;
+      for (int k = 16 * j; k < 16 * i; ++k) t = fma(M[16 * i + r][k], Wl[k][16 * j + c], t);
+      Tt[j][r][c] = t;
+    }
+    __syncthreads();
+    for (int e = tid; e < work; e += kCF) {
+      const int j = e >> 8, r = (e >> 4) & 15, c = e & 15, i = j + dist;
+      double t = 0.0;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) t = fma(Wl[16 * i + r][16 * i + m], Tt[j][m][c], t);
+      Wl[16 * i + r][16 * j + c] = -t;
+    }
+    __syncthreads();
+  }
+  double* W = Winv + (size_t)at * 4096;
+  for (int e = tid; e < 64 * 64; e += kCF) W[e] = Wl[e >> 6][e & 63];
 }
 
 // Panel below block kb: X = A21 L11^-T = A21 W^T on FP64 MFMA, 64 rows per
@@ -799,9 +834,9 @@ CovPlan cov_plan(int n, int d) {
   p.n = n;
   p.nb = (d + 15) / 16;
   p.blocks = p.nb * (p.nb + 1) / 2;
-  // about 1024 waves, at most 32 partials per block (the reduction is one
-  // workgroup), at least 64 particles per chunk
-  int chunks = (1024 + p.blocks - 1) / p.blocks;
+  // about 4096 waves, at most 32 partials per block (the last-arriving
+  // workgroup sums them), at least 64 particles per chunk
+  int chunks = (4096 + p.blocks - 1) / p.blocks;
   if (chunks > kMaxChunks) chunks = kMaxChunks;
   const int max_chunks = (n + 63) / 64;
   if (chunks > max_chunks) chunks = max_chunks;
@@ -814,10 +849,7 @@ CovPlan cov_plan(int n, int d) {
   return p;
 }
 
-int blocked_attempts(int d) {
-  if (d <= kSmallD) return 0;
-  return d <= 2048 ? kJitterAttempts : 3;
-}
+int blocked_attempts(int d) { return d <= kSmallD ? 0 : kJitterAttempts; }
 
 size_t blocked_scratch_doubles(int d) {
   const int P = blocked_attempts(d);
@@ -878,6 +910,7 @@ void launch_factor(const FactorArgs& a, hipStream_t s) {
     }
     bf_emit_kernel<<<nel, 256, 0, s>>>(a.A, a.Aspec, d, a.Bt, a.ldb, a.eps_ptr, a.tau_out,
                                        a.bstatus, P, a.err_out, a.done);
+    if (P >= kJitterAttempts) return;
   }
   factor_kernel<<<1, kFT, 0, s>>>(a);
 }

@@ -19,6 +19,8 @@
 //
 // Acceptances are counted per particle (no contended atomics) and summed
 // once at the end of the sweep.
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 #include "common.hpp"
@@ -31,9 +33,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kTM = 64, kTN = 64, kTK = 32;   // GEMM tile: particles x columns x K
-constexpr int kGT = 256;                       // GEMM threads (4 waves, 32 x 32 each)
 constexpr int kAT = 256;                       // accept threads per particle
 
 __device__ __forceinline__ unsigned short to16(float x, int prec) {
@@ -84,141 +85,209 @@ __global__ __launch_bounds__(256) void z_kernel(float* __restrict__ z, int n, in
 
 // ------------------------------------------------------------------ proposal
 
-// phi'[p][c] = phi[irow(p)][c] + (z Bt)[p][c] for a 64 x 64 tile.  LDS holds
-// the z tile as As[row][k] and the factor tile transposed as Bs[col][k]
-// (k contiguous), so that each lane reads its MFMA operands with vector
-// loads; the next K tile is loaded into registers while the current one is
-// multiplied.
+// Lp[c][k] = Bt[k][c] = eps L[c][k] for k <= c < d and zero elsewhere, as a
+// dz x dz array with k contiguous (float32, or rounded to bfloat16 /
+// float16): the factor in the same row layout as z, so that both operands
+// of the product load as contiguous 16-byte vectors.  Built once per sweep
+// through 32 x 32 LDS tiles (coalesced on both sides).
 template <int PREC>
-__global__ __launch_bounds__(kGT) void proposal_kernel(const float* __restrict__ zin,
-                                                       const float* __restrict__ Bt, int ldb,
-                                                       const float* __restrict__ phi,
-                                                       const int32_t* __restrict__ irows,
-                                                       float* __restrict__ prop, int n, int d,
-                                                       int dz, const int32_t* __restrict__ done) {
+__global__ __launch_bounds__(256) void lp_kernel(const float* __restrict__ Bt, int ldb, int d,
+                                                 int dz, void* __restrict__ lp,
+                                                 const int32_t* __restrict__ done) {
+  if (done && *done) return;
+  __shared__ float t[32][33];
+  const int k0 = blockIdx.y * 32, c0 = blockIdx.x * 32;   // Bt rows k, columns c
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int k = k0 + r, c = c0 + tx;
+    float v = 0.f;
+    if (k < d && c < d && k <= c) v = Bt[(size_t)k * ldb + c];
+    t[r][tx] = v;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int c = c0 + r, k = k0 + tx;   // Lp row c, column k
+    const float v = t[tx][r];
+    if constexpr (PREC == PHI4_FP32)
+      static_cast<float*>(lp)[(size_t)c * dz + k] = v;
+    else
+      static_cast<unsigned short*>(lp)[(size_t)c * dz + k] = to16(v, PREC);
+  }
+}
+
+// phi'[p][c] = phi[irow(p)][c] + sum_{k <= c} z[p][k] Lp[c][k].
+//
+// Workgroup tile BM particles x 64 columns, 4 waves as 2 x 2 (each BM/2 x 32
+// as 16 x 16 MFMA fragments), K in tiles of 64 through double-buffered LDS
+// (row stride padded by one 16-byte vector); global loads run two K tiles
+// ahead in two register sets, so that a load has two tiles of MFMA work to
+// land.  Column tiles are taken in pairs (x, J - 1 - x): tile j of the
+// triangular product has j + 1 K tiles, so every pair costs the same.
+//
+// float32 form: lane (p, g) of 16x16x4 step m supplies A[p][k], B[k][p] with
+// k = 16 kc + 4 g + m (one 16-byte LDS read feeds four steps; the order of
+// the sum is a permutation of k).  16-bit forms: 16x16x32 with
+// A[p][8g .. 8g+7] per lane, and (M(z) - M(-z)) / 2 so that the increment is
+// odd in z.
+template <int PREC, int BM>
+__global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
+                                                   const void* __restrict__ lpin,
+                                                   const float* __restrict__ phi,
+                                                   const int32_t* __restrict__ irows,
+                                                   float* __restrict__ prop, int n, int d,
+                                                   int dz, const int32_t* __restrict__ done) {
   if (done && *done) return;
   constexpr bool F32 = PREC == PHI4_FP32;
   using T = typename std::conditional<F32, float, unsigned short>::type;
-  constexpr int KS = kTK + (F32 ? 4 : 8);   // LDS row stride (elements)
-  __shared__ __align__(16) T As[2][kTM * KS];
-  __shared__ __align__(16) T Bs[2][kTN * KS];
+  constexpr int BN = 64, BK = 64;
+  constexpr int EPV = 16 / (int)sizeof(T);     // elements per 16-byte vector
+  constexpr int VPR = BK / EPV;                // vectors per tile row
+  constexpr int KS = BK + EPV;                 // LDS row stride (elements)
+  constexpr int AV = BM * VPR / 256, BV = BN * VPR / 256;
+  static_assert(AV >= 1 && BV >= 1, "tile too small for 256 threads");
+  constexpr int FM = BM / 32, FN = BN / 32;    // fragments per wave
+  __shared__ __align__(16) T As[2][BM * KS];
+  __shared__ __align__(16) T Bs[2][BN * KS];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int pl = lane & 15, gl = lane >> 4;
-  const int p0 = blockIdx.y * kTM, c0 = blockIdx.x * kTN;
-  const int wr = wv >> 1, wc = wv & 1;         // this wave's 32 x 32 sub-tile
-  const int kend = min(d, c0 + kTN);           // Bt[k][c] = 0 for k > c
-  const int nkt = (kend + kTK - 1) / kTK;
+  const int wr = wv >> 1, wc = wv & 1;
+  const int p0 = blockIdx.y * BM;
+  const int J = (d + BN - 1) / BN;
+  const int x = blockIdx.x;
+  const int ntile = (J - 1 - x > x) ? 2 : 1;
+  const T* z = static_cast<const T*>(zin);
+  const T* lp = static_cast<const T*>(lpin);
 
-  // staging assignments: A: 64 rows x 32 k; B: 32 k x 64 columns (float32 source)
-  const int ar = tid >> 2, aq = tid & 3;       // A row, 8-element quarter of the k range
-  const int bk = tid >> 3, bc = (tid & 7) * 8; // B row k, 8 consecutive columns
-  const T* zt = reinterpret_cast<const T*>(zin);
-  const int arow = min(p0 + ar, n - 1);        // valid address; rows beyond n unused
-  T ra[8];
-  float rb[8];
-  auto load_tile = [&](int kt) {
-    const int k0 = kt * kTK;
-    const T* src = zt + (size_t)arow * dz + k0 + 8 * aq;   // dz >= k0 + 32 (padded)
+  u32x4 ra0[AV], rb0[BV], ra1[AV], rb1[BV];
+  auto gload = [&](u32x4(&ra)[AV], u32x4(&rb)[BV], int c0, int kt) __attribute__((always_inline)) {
+    const int k0 = kt * BK;
+#pragma unroll
+    for (int i = 0; i < AV; ++i) {
+      const int v = tid + 256 * i, row = v / VPR, vc = v % VPR;
+      ra[i] = *reinterpret_cast<const u32x4*>(z + (size_t)min(p0 + row, n - 1) * dz + k0 +
+                                              vc * EPV);
+    }
+#pragma unroll
+    for (int i = 0; i < BV; ++i) {
+      const int v = tid + 256 * i, row = v / VPR, vc = v % VPR;
+      rb[i] = *reinterpret_cast<const u32x4*>(lp + (size_t)min(c0 + row, dz - 1) * dz + k0 +
+                                              vc * EPV);
+    }
+  };
+  auto sstore = [&](const u32x4(&ra)[AV], const u32x4(&rb)[BV], int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < AV; ++i) {
+      const int v = tid + 256 * i, row = v / VPR, vc = v % VPR;
+      *reinterpret_cast<u32x4*>(&As[buf][row * KS + vc * EPV]) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < BV; ++i) {
+      const int v = tid + 256 * i, row = v / VPR, vc = v % VPR;
+      *reinterpret_cast<u32x4*>(&Bs[buf][row * KS + vc * EPV]) = rb[i];
+    }
+  };
+
+  f32x4 acc[FM][FN], accn[FM][FN];
+  auto compute = [&](int buf) __attribute__((always_inline)) {
     if constexpr (F32) {
-      const float4 x0 = *reinterpret_cast<const float4*>(src);
-      const float4 x1 = *reinterpret_cast<const float4*>(src + 4);
-      ra[0] = x0.x; ra[1] = x0.y; ra[2] = x0.z; ra[3] = x0.w;
-      ra[4] = x1.x; ra[5] = x1.y; ra[6] = x1.z; ra[7] = x1.w;
+#pragma unroll
+      for (int kc = 0; kc < BK / 16; ++kc) {
+        float4 af[FM], bf[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+          af[i] = *reinterpret_cast<const float4*>(
+              &As[buf][(wr * (BM / 2) + 16 * i + pl) * KS + 16 * kc + 4 * gl]);
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          bf[j] = *reinterpret_cast<const float4*>(
+              &Bs[buf][(wc * 32 + 16 * j + pl) * KS + 16 * kc + 4 * gl]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i].x, bf[j].x, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i].y, bf[j].y, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i].z, bf[j].z, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i].w, bf[j].w, acc[i][j], 0, 0, 0);
+          }
+      }
     } else {
-      const u16x8 x = *reinterpret_cast<const u16x8*>(src);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) ra[e] = x[e];
-    }
-    const int k = k0 + bk;
+      for (int kc = 0; kc < BK / 32; ++kc) {
+        u16x8 af[FM], bf[FN];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int c = c0 + bc + e;
-      const float v = Bt[(size_t)min(k, d - 1) * ldb + min(c, d - 1)];
-      rb[e] = (k < d && c < d) ? v : 0.f;
-    }
-  };
-  auto store_tile = [&](int buf) {
+        for (int i = 0; i < FM; ++i)
+          af[i] = *reinterpret_cast<const u16x8*>(
+              &As[buf][(wr * (BM / 2) + 16 * i + pl) * KS + 32 * kc + 8 * gl]);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) As[buf][ar * KS + 8 * aq + e] = ra[e];
+        for (int j = 0; j < FN; ++j)
+          bf[j] = *reinterpret_cast<const u16x8*>(
+              &Bs[buf][(wc * 32 + 16 * j + pl) * KS + 32 * kc + 8 * gl]);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      if constexpr (F32)
-        Bs[buf][(bc + e) * KS + bk] = rb[e];
-      else
-        Bs[buf][(bc + e) * KS + bk] = to16(rb[e], PREC);
-    }
-  };
-
-  f32x4 acc[2][2], accn[2][2];
+        for (int i = 0; i < FM; ++i) {
+          const u16x8 an = af[i] ^ (unsigned short)0x8000u;   // -z, exact
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = accn[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  if (nkt > 0) {
-    load_tile(0);
-    store_tile(0);
-  }
-  __syncthreads();
-  for (int kt = 0; kt < nkt; ++kt) {
-    const int cb = kt & 1;
-    if (kt + 1 < nkt) load_tile(kt + 1);
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int row = 32 * wr + 16 * i + pl;
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int col = 32 * wc + 16 * j + pl;
-        if constexpr (F32) {
-          // lane (p, g) supplies A[p][k] and B[k][p] for k = 4 m + g
-#pragma unroll
-          for (int m = 0; m < kTK / 4; ++m) {
-            const float av = As[cb][row * KS + 4 * m + gl];
-            const float bv = Bs[cb][col * KS + 4 * m + gl];
-            if (m & 1)
-              accn[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, accn[i][j], 0, 0, 0);
-            else
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[i][j], 0, 0, 0);
-          }
-        } else {
-          // lane (p, g) supplies A[p][8g .. 8g+7] and B[8g .. 8g+7][p]
-          const u16x8 za = *reinterpret_cast<const u16x8*>(&As[cb][row * KS + 8 * gl]);
-          const u16x8 zn = za ^ (unsigned short)0x8000u;   // -z, exact
-          const u16x8 b = *reinterpret_cast<const u16x8*>(&Bs[cb][col * KS + 8 * gl]);
-          if constexpr (PREC == PHI4_BF16) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                __builtin_bit_cast(bf16x8, za), __builtin_bit_cast(bf16x8, b), acc[i][j], 0, 0, 0);
-            accn[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                __builtin_bit_cast(bf16x8, zn), __builtin_bit_cast(bf16x8, b), accn[i][j], 0, 0, 0);
-          } else {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-                __builtin_bit_cast(f16x8, za), __builtin_bit_cast(f16x8, b), acc[i][j], 0, 0, 0);
-            accn[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-                __builtin_bit_cast(f16x8, zn), __builtin_bit_cast(f16x8, b), accn[i][j], 0, 0, 0);
+          for (int j = 0; j < FN; ++j) {
+            if constexpr (PREC == PHI4_BF16) {
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  __builtin_bit_cast(bf16x8, af[i]), __builtin_bit_cast(bf16x8, bf[j]), acc[i][j],
+                  0, 0, 0);
+              accn[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  __builtin_bit_cast(bf16x8, an), __builtin_bit_cast(bf16x8, bf[j]), accn[i][j],
+                  0, 0, 0);
+            } else {
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                  __builtin_bit_cast(f16x8, af[i]), __builtin_bit_cast(f16x8, bf[j]), acc[i][j],
+                  0, 0, 0);
+              accn[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                  __builtin_bit_cast(f16x8, an), __builtin_bit_cast(f16x8, bf[j]), accn[i][j],
+                  0, 0, 0);
+            }
           }
         }
       }
     }
-    if (kt + 1 < nkt) store_tile(cb ^ 1);
+  };
+
+  for (int tt = 0; tt < ntile; ++tt) {
+    const int c0 = (tt ? J - 1 - x : x) * BN;
+    const int nkt = (min(d, c0 + BN) + BK - 1) / BK;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[i][j] = accn[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    gload(ra0, rb0, c0, 0);
+    sstore(ra0, rb0, 0);
+    if (nkt > 1) gload(ra1, rb1, c0, 1);
     __syncthreads();
-  }
-  // epilogue: result item r of lane (p, g) is row 4g + r, column p
+    for (int kt = 0; kt < nkt; kt += 2) {
+      if (kt + 2 < nkt) gload(ra0, rb0, c0, kt + 2);
+      compute(0);
+      if (kt + 1 < nkt) sstore(ra1, rb1, 1);
+      __syncthreads();
+      if (kt + 1 >= nkt) break;
+      if (kt + 3 < nkt) gload(ra1, rb1, c0, kt + 3);
+      compute(1);
+      if (kt + 2 < nkt) sstore(ra0, rb0, 0);
+      __syncthreads();
+    }
+    // epilogue: result item r of lane (p, g) is row 4g + r, column p
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int c = c0 + 32 * wc + 16 * j + pl;
+      for (int j = 0; j < FN; ++j) {
+        const int c = c0 + wc * 32 + 16 * j + pl;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int p = p0 + 32 * wr + 16 * i + 4 * gl + r;
-        if (p < n && c < d) {
-          const float inc = F32 ? acc[i][j][r] + accn[i][j][r]
-                                : 0.5f * (acc[i][j][r] - accn[i][j][r]);
-          const int ir = irows ? irows[p] : p;
-          prop[(size_t)p * d + c] = phi[(size_t)ir * d + c] + inc;
+        for (int r = 0; r < 4; ++r) {
+          const int p = p0 + wr * (BM / 2) + 16 * i + 4 * gl + r;
+          if (p < n && c < d) {
+            const float inc = F32 ? acc[i][j][r] : 0.5f * (acc[i][j][r] - accn[i][j][r]);
+            const int ir = irows ? irows[p] : p;
+            prop[(size_t)p * d + c] = phi[(size_t)ir * d + c] + inc;
+          }
         }
       }
-    }
+  }
 }
 
 // ------------------------------------------------------------------ accept
@@ -354,7 +423,22 @@ __global__ void clear_i32_kernel(int32_t* x, int n) {
 }
 
 template <int PREC>
-void enqueue_step(const MutateArgs& a, const LargeScratch& w, int s, bool first, hipStream_t st) {
+void launch_gemm(int bm, const LargeScratch& w, const float* cur, const int32_t* crows, int n,
+                 int d, const int32_t* done, hipStream_t st) {
+  const int dz = large_dz(d);
+  const int J = (d + 63) / 64;
+  const dim3 grid((unsigned)((J + 1) / 2), (unsigned)((n + bm - 1) / bm));
+  if (bm == 32)
+    gemm_kernel<PREC, 32><<<grid, 256, 0, st>>>(w.z, w.lp, cur, crows, w.prop, n, d, dz, done);
+  else if (bm == 128)
+    gemm_kernel<PREC, 128><<<grid, 256, 0, st>>>(w.z, w.lp, cur, crows, w.prop, n, d, dz, done);
+  else
+    gemm_kernel<PREC, 64><<<grid, 256, 0, st>>>(w.z, w.lp, cur, crows, w.prop, n, d, dz, done);
+}
+
+template <int PREC>
+void enqueue_step(const MutateArgs& a, const LargeScratch& w, int bm, int s, bool first,
+                  hipStream_t st) {
   const int n = a.n, d = a.d, dz = large_dz(d);
   const uint32_t step = (uint32_t)(a.step0 + s);
   const long long nz = (long long)n * (dz / 4);
@@ -364,9 +448,7 @@ void enqueue_step(const MutateArgs& a, const LargeScratch& w, int s, bool first,
   // current fields: the step-0 source (through its row maps) or the output
   const float* cur = first ? a.src : a.dst;
   const int32_t* crows = first ? (a.src_rows ? a.src_rows : a.rows) : a.rows;
-  const dim3 grid((unsigned)((d + kTN - 1) / kTN), (unsigned)((n + kTM - 1) / kTM));
-  proposal_kernel<PREC><<<grid, kGT, 0, st>>>(w.z, a.Bt, a.ldb, cur, crows, w.prop, n, d, dz,
-                                               a.done_ptr);
+  launch_gemm<PREC>(bm, w, cur, crows, n, d, a.done_ptr, st);
   AcceptArgs aa = {};
   aa.cur = cur;
   aa.crows = crows;
@@ -402,13 +484,91 @@ void enqueue_step(const MutateArgs& a, const LargeScratch& w, int s, bool first,
     accept_kernel<false><<<n, kAT, lds, st>>>(aa);
 }
 
+constexpr int kTileChoices[3] = {32, 64, 128};
+
+// Particle-tile height of the proposal product per (device, n, d, precision):
+// timed once per shape on the caller's stream (hipEvents, three launches of
+// each choice after one warm-up) and kept for the process.  Inside a stream
+// capture nothing can be timed; the choice is then the largest height that
+// still gives every compute unit two workgroups, and it is not kept.
+struct TileKey {
+  int dev, n, d, prec;
+  bool operator<(const TileKey& o) const {
+    if (dev != o.dev) return dev < o.dev;
+    if (n != o.n) return n < o.n;
+    if (d != o.d) return d < o.d;
+    return prec < o.prec;
+  }
+};
+std::mutex g_tile_mu;
+std::map<TileKey, int> g_tiles;
+
+int heuristic_tile(int n, int d) {
+  const int pairs = ((d + 63) / 64 + 1) / 2;
+  for (int bm : {128, 64})
+    if ((long long)pairs * ((n + bm - 1) / bm) >= 512) return bm;
+  return 32;
+}
+
+template <int PREC>
+int tune_tile(const LargeScratch& w, int n, int d, hipStream_t st) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return heuristic_tile(n, d);
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return heuristic_tile(n, d);
+  }
+  int best = heuristic_tile(n, d);
+  float best_ms = 1e30f;
+  for (int bm : kTileChoices) {
+    // operands: whatever the scratch holds (timing only); prop doubles as phi
+    launch_gemm<PREC>(bm, w, w.prop, nullptr, n, d, nullptr, st);
+    (void)hipEventRecord(e0, st);
+    for (int r = 0; r < 3; ++r) launch_gemm<PREC>(bm, w, w.prop, nullptr, n, d, nullptr, st);
+    (void)hipEventRecord(e1, st);
+    float ms = 0.f;
+    if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
+        ms < best_ms) {
+      best_ms = ms;
+      best = bm;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best;
+}
+
+int gemm_tile(const LargeScratch& w, int n, int d, int prec, hipStream_t st) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const TileKey key{dev, n, d, prec};
+  {
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    auto it = g_tiles.find(key);
+    if (it != g_tiles.end()) return it->second;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+    return heuristic_tile(n, d);
+  int bm;
+  switch (prec) {
+    case PHI4_BF16: bm = tune_tile<PHI4_BF16>(w, n, d, st); break;
+    case PHI4_FP16: bm = tune_tile<PHI4_FP16>(w, n, d, st); break;
+    default: bm = tune_tile<PHI4_FP32>(w, n, d, st); break;
+  }
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  g_tiles[key] = bm;
+  return bm;
+}
+
 }  // namespace
 
 int large_dz(int d) { return (d + 63) / 64 * 64; }
 
 size_t large_scratch_bytes(int n, int d) {
-  return (size_t)n * large_dz(d) * sizeof(float) + (size_t)n * d * sizeof(float) +
-         (size_t)n * sizeof(int32_t) + 3 * 256;
+  const size_t dz = (size_t)large_dz(d);
+  return (size_t)n * dz * sizeof(float) + (size_t)n * d * sizeof(float) +
+         (size_t)n * sizeof(int32_t) + dz * dz * sizeof(float) + 4 * 256;
 }
 
 LargeScratch large_scratch(void* base, int n, int d) {
@@ -419,14 +579,24 @@ LargeScratch large_scratch(void* base, int n, int d) {
     p += (bytes + 255) / 256 * 256;
     return r;
   };
-  w.z = reinterpret_cast<float*>(take((size_t)n * large_dz(d) * sizeof(float)));
+  const size_t dz = (size_t)large_dz(d);
+  w.z = reinterpret_cast<float*>(take((size_t)n * dz * sizeof(float)));
   w.prop = reinterpret_cast<float*>(take((size_t)n * d * sizeof(float)));
   w.accp = reinterpret_cast<int32_t*>(take((size_t)n * sizeof(int32_t)));
+  w.lp = take(dz * dz * sizeof(float));
   return w;
 }
 
 void launch_large_init(const LargeScratch& w, int n, hipStream_t s) {
   if (n > 0 && w.accp) clear_i32_kernel<<<(n + 255) / 256, 256, 0, s>>>(w.accp, n);
+}
+
+int large_tile_choice(int n, int d, int precision) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  auto it = g_tiles.find(TileKey{dev, n, d, precision});
+  return it == g_tiles.end() ? 0 : it->second;
 }
 
 // One sweep: n_steps steps of normals, proposal and accept.  A sweep of zero
@@ -436,12 +606,24 @@ int launch_mutate_large(const MutateArgs& a, const LargeScratch& w, int precisio
   const bool moves = a.src != a.dst || a.src_rows != nullptr;
   if (a.n_steps == 0 && !moves) return PHI4_OK;
   const int steps = a.n_steps > 0 ? a.n_steps : 1;
+  if (precision != PHI4_FP32 && precision != PHI4_BF16 && precision != PHI4_FP16)
+    return PHI4_EINVAL;
+  const int bm = gemm_tile(w, a.n, a.d, precision, s);
+  {
+    const int dz = large_dz(a.d);
+    const dim3 g((unsigned)(dz / 32), (unsigned)(dz / 32));
+    if (precision == PHI4_FP32)
+      lp_kernel<PHI4_FP32><<<g, 256, 0, s>>>(a.Bt, a.ldb, a.d, dz, w.lp, a.done_ptr);
+    else if (precision == PHI4_BF16)
+      lp_kernel<PHI4_BF16><<<g, 256, 0, s>>>(a.Bt, a.ldb, a.d, dz, w.lp, a.done_ptr);
+    else
+      lp_kernel<PHI4_FP16><<<g, 256, 0, s>>>(a.Bt, a.ldb, a.d, dz, w.lp, a.done_ptr);
+  }
   for (int t = 0; t < steps; ++t) {
     switch (precision) {
-      case PHI4_FP32: enqueue_step<PHI4_FP32>(a, w, t, t == 0, s); break;
-      case PHI4_BF16: enqueue_step<PHI4_BF16>(a, w, t, t == 0, s); break;
-      case PHI4_FP16: enqueue_step<PHI4_FP16>(a, w, t, t == 0, s); break;
-      default: return PHI4_EINVAL;
+      case PHI4_FP32: enqueue_step<PHI4_FP32>(a, w, bm, t, t == 0, s); break;
+      case PHI4_BF16: enqueue_step<PHI4_BF16>(a, w, bm, t, t == 0, s); break;
+      default: enqueue_step<PHI4_FP16>(a, w, bm, t, t == 0, s); break;
     }
   }
   if (a.prop && a.n_steps > 0) {

@@ -678,6 +678,23 @@ __global__ __launch_bounds__(kRT) void mean_abs_kernel(const float* absM, int n,
   if (threadIdx.x == 0) *out = s / n;
 }
 
+// Level, beta and error of many SMC runs gathered into one array (the
+// status word of a batched launch).
+__global__ __launch_bounds__(64) void batch_status_kernel(const SmcState* const* __restrict__ st,
+                                                          int runs,
+                                                          BatchStatus* __restrict__ out) {
+  const int r = blockIdx.x * 64 + threadIdx.x;
+  if (r >= runs) return;
+  const SmcState* s = st[r];
+  BatchStatus b;
+  b.beta = s->beta;
+  b.level = s->level;
+  b.done = s->done;
+  b.err = s->err;
+  b.pad = 0;
+  out[r] = b;
+}
+
 }  // namespace
 
 void launch_reweight(const ReweightArgs& a, hipStream_t s) {
@@ -707,6 +724,10 @@ void launch_smc_state_init(SmcState* st, double eps0, double acc_target, double 
 
 void launch_ns_state_init(NsState* st, double eps0, double acc_target, hipStream_t s) {
   ns_state_init_kernel<<<1, 1, 0, s>>>(st, eps0, acc_target);
+}
+
+void launch_batch_status(const SmcState* const* st, int runs, BatchStatus* out, hipStream_t s) {
+  if (runs > 0) batch_status_kernel<<<(runs + 63) / 64, 64, 0, s>>>(st, runs, out);
 }
 
 void launch_mean_abs(const float* absM, int n, double* out, const int32_t* done, hipStream_t s) {

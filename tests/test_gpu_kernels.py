@@ -190,7 +190,7 @@ def test_covariance_row_subset():
 
 
 @pytest.mark.parametrize("d,cond", [(1, 1.0), (16, 1e3), (64, 1e4), (100, 1e2), (256, 1e3),
-                                    (300, 1e3), (1024, 1e2)])
+                                    (300, 1e3), (1024, 1e2), (2100, 1e2), (4096, 1e2)])
 def test_cholesky_matches_oracle(d, cond):
     say("chol", d)
     A = synth.spd_matrix(d + 1, d, cond=cond)
@@ -218,7 +218,7 @@ def test_cholesky_jitter_and_failure():
     assert e.value.code == P.PHI4_ECHOL
 
 
-@pytest.mark.parametrize("d", [100, 324])
+@pytest.mark.parametrize("d", [100, 324, 1156])
 def test_blocked_cholesky_jitter_escalation(d):
     """Rank-deficient covariance (d > 64): the blocked first attempt fails and
     the escalation reaches the oracle's tau and factor."""
