@@ -36,6 +36,24 @@ SLOTS_PER_SITE = 30.0 + 11.5 + 22.0
 # VALU issue rate of the chip: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 VALU_PEAK = 256 * 4 * 16 * 2.4e9
 
+# HBM bytes per launch of the fused sweep at this workload, from two rocprofv3
+# counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0: the factors that make a
+# 256 MiB device-to-device copy read and write 256 MiB on the same counters),
+# valid only for the kernel sources they were taken on.
+TRAFFIC = dict(bytes_per_launch=(517.48 * 1.99983 + 1072.0) * 1024,
+               sources={"k_mutate.hip": "465e716a1e2bc9b9717a2032a856dd850a4dbd3a6daaf2735f3d5cb52bb5dbd7",
+                        "common.hpp": "4b8e9970df8aa2e23ccc28d4b942b11777cc1a6942cb635f059822ebb0d416a7"})
+
+
+def traffic_per_launch():
+    import hashlib
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2511_15196_amd", "csrc")
+    for name, digest in TRAFFIC["sources"].items():
+        with open(os.path.join(csrc, name), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    return TRAFFIC["bytes_per_launch"]
+
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
@@ -205,6 +223,36 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# The paper's SMC-RW runs on one NVIDIA L4 (Table 2): wall-clock seconds and
+# log Z at m0^2 = -4, lambda = 1, N = 5000, 3V steps per level, ESS 0.9.
+PAPER_SMC_RW_L4 = {10: (6.7, -65.2), 15: (21.5, -146.4), 18: (46.0, -209.9)}
+
+
+def paper_point(P, torch, sizes=(10, 15, 18), seed=0):
+    """SMC-RW at the paper's own settings, timed end to end on this GPU."""
+    out = {}
+    for L in sizes:
+        d = L * L
+        warm = P.SMC(L, 5000, -4.0, 1.0, ess_frac=0.9, n_steps=1, seed=seed + 1000)
+        P.smc_reweight_resample(warm.h)
+        P.smc_mutate(warm.h)
+        warm.close()
+        smc = P.SMC(L, 5000, -4.0, 1.0, ess_frac=0.9, n_steps=3 * d, seed=seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, lv = smc.run()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ref_s, ref_z = PAPER_SMC_RW_L4[L]
+        out[f"L{L}"] = dict(seconds=wall, levels=lv, logz=smc.logz(),
+                            mean_abs_m=smc.observables()["mean_abs_m"],
+                            value=lv * 5000 * 3 * d / wall,
+                            paper_L4_seconds=ref_s, paper_L4_logz=ref_z)
+        smc.close()
+        progress(f"paper point L={L} done")
+    return out
+
+
 def extra_workloads(P, torch):
     """Free-theory check of the main workload, SMC at L = 16 and NS at L = 32."""
     ex = {}
@@ -222,6 +270,7 @@ def extra_workloads(P, torch):
     for prec in ("fp32", "bf16"):
         ex[f"ns_L32_n4096_k2048_{prec}"] = ns_workload(P, torch, 32, 4096, 2048, 40, prec, 8)
         progress(f"NS L=32 {prec} done")
+    ex["paper_point_smc_rw"] = paper_point(P, torch)
     return ex
 
 
@@ -289,7 +338,7 @@ def main():
         "mutate_kernel_us": k_avg * 1e6,
         "mutate_kernel_share": r["kernel_ms"] * 1e-3 / r["wall"],
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                     "unit": "TOP/s", "frac": achieved / VALU_PEAK, "traffic": None,
+                     "unit": "TOP/s", "frac": achieved / VALU_PEAK, "traffic": traffic_per_launch(),
                      "kernel": "mutate_kernel<DP=64,W=4,fp32>",
                      "mfma_tflops": mfma_tflops},
     }

@@ -99,14 +99,20 @@ __global__ __launch_bounds__(64) void cov_partial_kernel(const float* __restrict
     m1 += __shfl_xor(m1, 32, 64);
     if (g == 0) w.part1[(size_t)chunk * p.nb * 16 + sr] = m1;
   }
-  // The last chunk of this block to arrive sums the block's partials over the
-  // chunks in chunk order (float64) and resets the counter; the others exit.
-  __threadfence();
-  int old = 0;
-  if (lane == 0) old = atomicAdd(&w.cnt[blk], 1);
-  old = __builtin_amdgcn_readfirstlane(old);
-  if (old != p.chunks - 1) return;
-  __threadfence();
+}
+
+// Sums each block's partials over the chunks in chunk order (float64) into
+// fin / fin1.  A kernel of its own: summing in the last-arriving chunk
+// workgroup needs an agent-scope fence per workgroup, which on a chip of
+// several L2 caches costs more than this launch.
+__global__ __launch_bounds__(64) void cov_sum_kernel(CovPlan p, float* __restrict__ part,
+                                                     const int32_t* __restrict__ done) {
+  if (done && *done) return;
+  const int blk = blockIdx.x, lane = threadIdx.x;
+  int bi = 0;
+  while ((bi + 1) * (bi + 2) / 2 <= blk) ++bi;
+  const int bj = blk - bi * (bi + 1) / 2;
+  const CovWork w = cov_work(part, p);
   {
     // every partial of the block in flight at once (one round trip)
     float x[4][kMaxChunks];
@@ -133,7 +139,6 @@ __global__ __launch_bounds__(64) void cov_partial_kernel(const float* __restrict
     for (int c = 0; c < kMaxChunks; ++c) m += c < p.chunks ? (double)x[c] : 0.0;
     w.fin1[16 * bi + lane] = m;
   }
-  if (lane == 0) w.cnt[blk] = 0;
 }
 
 __global__ void cov_init_kernel(int32_t* cnt, int blocks) {
@@ -834,8 +839,8 @@ CovPlan cov_plan(int n, int d) {
   p.n = n;
   p.nb = (d + 15) / 16;
   p.blocks = p.nb * (p.nb + 1) / 2;
-  // about 4096 waves, at most 32 partials per block (the last-arriving
-  // workgroup sums them), at least 64 particles per chunk
+  // about 4096 waves, at most 32 partials per block (cov_sum_kernel sums
+  // them in one round trip), at least 64 particles per chunk
   int chunks = (4096 + p.blocks - 1) / p.blocks;
   if (chunks > kMaxChunks) chunks = kMaxChunks;
   const int max_chunks = (n + 63) / 64;
@@ -870,6 +875,7 @@ void launch_cov_init(float* part, const CovPlan& p, hipStream_t s) {
 void launch_cov_partials(const float* phi, const int32_t* rows, const CovPlan& p, float* part,
                          const int32_t* done, hipStream_t s) {
   cov_partial_kernel<<<dim3(p.blocks, p.chunks), 64, 0, s>>>(phi, rows, p, part, done);
+  cov_sum_kernel<<<p.blocks, 64, 0, s>>>(p, part, done);
 }
 
 void launch_factor(const FactorArgs& a, hipStream_t s) {
