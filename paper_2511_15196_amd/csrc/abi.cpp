@@ -58,9 +58,9 @@ double default_eps0(int d, double eps0) { return eps0 > 0 ? eps0 : 2.38 / std::s
 
 // Scratch of the three-pass sweep for n particles.
 LargeScratch take_large(Carver& cv, int n, int d) {
-  if (n <= 0) return LargeScratch{nullptr, nullptr, nullptr, nullptr};
+  if (n <= 0) return LargeScratch{nullptr, nullptr, nullptr, nullptr, nullptr};
   void* base = cv.take<char>(large_scratch_bytes(n, d));
-  return cv.base ? large_scratch(base, n, d) : LargeScratch{nullptr, nullptr, nullptr, nullptr};
+  return cv.base ? large_scratch(base, n, d) : LargeScratch{nullptr, nullptr, nullptr, nullptr, nullptr};
 }
 
 // ------------------------------------------------------------------ SMC

@@ -244,13 +244,15 @@ struct NsState {
 
 // Scratch of the large-lattice sweep (k_large.hip) for n particles: normals
 // (n x large_dz(d) floats), proposals (n x d floats), per-particle
-// acceptance counts (n int32, zero between sweeps) and the factor in the
-// operand layout of the proposal product (large_dz(d)^2 floats).
+// acceptance counts (n int32, zero between sweeps), the factor in the
+// operand layout of the proposal product (large_dz(d)^2 floats) and the sign
+// bit of each row's first normal (n uint16, 16-bit forms).
 struct LargeScratch {
   float* z;
   float* prop;
   int32_t* accp;
   void* lp;
+  unsigned short* zsgn;
 };
 
 struct MutateArgs {

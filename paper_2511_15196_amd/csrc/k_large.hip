@@ -8,8 +8,9 @@
 //   2. proposal: phi'[p][c] = phi[p][c] + sum_{k <= c} z[p][k] Bt[k][c] on the
 //      matrix cores, 64 x 64 output tiles staged through LDS, only the
 //      K range on or above the diagonal of the triangular factor; the
-//      16-bit forms take (M(z) - M(-z)) / 2 so that the increment is odd
-//      in z (exactly symmetric proposal, no Hastings term);
+//      16-bit forms take s M(s z) with s the sign of the row's first
+//      normal, so that the increment is odd in z (exactly symmetric
+//      proposal, no Hastings term) at the cost of one product;
 //   3. accept: one workgroup per particle stages phi and phi' in LDS, forms
 //      S(phi), S(phi') and dS as a sum of per-site differences (Sec. 2
 //      Eq. (1)), dU0 = (|phi'|^2 - |phi|^2) / 2, tests the tempered
@@ -54,6 +55,7 @@ __global__ __launch_bounds__(256) void z_kernel(float* __restrict__ z, int n, in
                                                 const int32_t* __restrict__ rows, uint32_t step,
                                                 int level, const int32_t* __restrict__ level_ptr,
                                                 uint32_t seed, uint32_t run, float zsign,
+                                                unsigned short* __restrict__ zsgn,
                                                 const int32_t* __restrict__ done) {
   if (done && *done) return;
   const uint32_t c3 = counter3((uint32_t)(level_ptr ? *level_ptr : level), PHI4_PROPOSE);
@@ -80,6 +82,7 @@ __global__ __launch_bounds__(256) void z_kernel(float* __restrict__ z, int n, in
     h.z = to16(v.z, PREC);
     h.w = to16(v.w, PREC);
     *reinterpret_cast<ushort4*>(zh + (size_t)p * dz + 4 * q) = h;
+    if (q == 0) zsgn[p] = h.x & 0x8000u;   // sign bit of the row's first normal
   }
 }
 
@@ -127,10 +130,14 @@ __global__ __launch_bounds__(256) void lp_kernel(const float* __restrict__ Bt, i
 // float32 form: lane (p, g) of 16x16x4 step m supplies A[p][k], B[k][p] with
 // k = 16 kc + 4 g + m (one 16-byte LDS read feeds four steps; the order of
 // the sum is a permutation of k).  16-bit forms: 16x16x32 with
-// A[p][8g .. 8g+7] per lane, and (M(z) - M(-z)) / 2 so that the increment is
-// odd in z.
+// A[p][8g .. 8g+7] per lane; row p of z enters with its sign flipped when
+// the row's first normal is negative (s = -1, an exact bit flip) and the
+// result is multiplied by s: the increment s M(s z) is odd in z bit for bit
+// (negating z flips s), which the rounding inside the 16-bit dot products
+// alone does not guarantee.
 template <int PREC, int BM>
 __global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
+                                                   const unsigned short* __restrict__ zsgn,
                                                    const void* __restrict__ lpin,
                                                    const float* __restrict__ phi,
                                                    const int32_t* __restrict__ irows,
@@ -159,6 +166,14 @@ __global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
   const T* lp = static_cast<const T*>(lpin);
 
   u32x4 ra0[AV], rb0[BV], ra1[AV], rb1[BV];
+  // 16-bit forms: sign masks of this thread's A rows (both halves of a word)
+  unsigned int amask[AV];
+#pragma unroll
+  for (int i = 0; i < AV; ++i) {
+    const int row = (tid + 256 * i) / VPR;
+    const unsigned int m = F32 ? 0u : (unsigned int)zsgn[min(p0 + row, n - 1)];
+    amask[i] = m | (m << 16);
+  }
   auto gload = [&](u32x4(&ra)[AV], u32x4(&rb)[BV], int c0, int kt) __attribute__((always_inline)) {
     const int k0 = kt * BK;
 #pragma unroll
@@ -178,7 +193,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
 #pragma unroll
     for (int i = 0; i < AV; ++i) {
       const int v = tid + 256 * i, row = v / VPR, vc = v % VPR;
-      *reinterpret_cast<u32x4*>(&As[buf][row * KS + vc * EPV]) = ra[i];
+      *reinterpret_cast<u32x4*>(&As[buf][row * KS + vc * EPV]) = F32 ? ra[i] : (ra[i] ^ amask[i]);
     }
 #pragma unroll
     for (int i = 0; i < BV; ++i) {
@@ -187,7 +202,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
     }
   };
 
-  f32x4 acc[FM][FN], accn[FM][FN];
+  f32x4 acc[FM][FN];
   auto compute = [&](int buf) __attribute__((always_inline)) {
     if constexpr (F32) {
 #pragma unroll
@@ -224,27 +239,18 @@ __global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
           bf[j] = *reinterpret_cast<const u16x8*>(
               &Bs[buf][(wc * 32 + 16 * j + pl) * KS + 32 * kc + 8 * gl]);
 #pragma unroll
-        for (int i = 0; i < FM; ++i) {
-          const u16x8 an = af[i] ^ (unsigned short)0x8000u;   // -z, exact
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
           for (int j = 0; j < FN; ++j) {
-            if constexpr (PREC == PHI4_BF16) {
+            if constexpr (PREC == PHI4_BF16)
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                   __builtin_bit_cast(bf16x8, af[i]), __builtin_bit_cast(bf16x8, bf[j]), acc[i][j],
                   0, 0, 0);
-              accn[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                  __builtin_bit_cast(bf16x8, an), __builtin_bit_cast(bf16x8, bf[j]), accn[i][j],
-                  0, 0, 0);
-            } else {
+            else
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
                   __builtin_bit_cast(f16x8, af[i]), __builtin_bit_cast(f16x8, bf[j]), acc[i][j],
                   0, 0, 0);
-              accn[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-                  __builtin_bit_cast(f16x8, an), __builtin_bit_cast(f16x8, bf[j]), accn[i][j],
-                  0, 0, 0);
-            }
           }
-        }
       }
     }
   };
@@ -255,7 +261,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
-      for (int j = 0; j < FN; ++j) acc[i][j] = accn[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     gload(ra0, rb0, c0, 0);
     sstore(ra0, rb0, 0);
     if (nkt > 1) gload(ra1, rb1, c0, 1);
@@ -281,7 +287,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
         for (int r = 0; r < 4; ++r) {
           const int p = p0 + wr * (BM / 2) + 16 * i + 4 * gl + r;
           if (p < n && c < d) {
-            const float inc = F32 ? acc[i][j][r] : 0.5f * (acc[i][j][r] - accn[i][j][r]);
+            const float inc = (F32 || !zsgn[p]) ? acc[i][j][r] : -acc[i][j][r];
             const int ir = irows ? irows[p] : p;
             prop[(size_t)p * d + c] = phi[(size_t)ir * d + c] + inc;
           }
@@ -429,11 +435,11 @@ void launch_gemm(int bm, const LargeScratch& w, const float* cur, const int32_t*
   const int J = (d + 63) / 64;
   const dim3 grid((unsigned)((J + 1) / 2), (unsigned)((n + bm - 1) / bm));
   if (bm == 32)
-    gemm_kernel<PREC, 32><<<grid, 256, 0, st>>>(w.z, w.lp, cur, crows, w.prop, n, d, dz, done);
+    gemm_kernel<PREC, 32><<<grid, 256, 0, st>>>(w.z, w.zsgn, w.lp, cur, crows, w.prop, n, d, dz, done);
   else if (bm == 128)
-    gemm_kernel<PREC, 128><<<grid, 256, 0, st>>>(w.z, w.lp, cur, crows, w.prop, n, d, dz, done);
+    gemm_kernel<PREC, 128><<<grid, 256, 0, st>>>(w.z, w.zsgn, w.lp, cur, crows, w.prop, n, d, dz, done);
   else
-    gemm_kernel<PREC, 64><<<grid, 256, 0, st>>>(w.z, w.lp, cur, crows, w.prop, n, d, dz, done);
+    gemm_kernel<PREC, 64><<<grid, 256, 0, st>>>(w.z, w.zsgn, w.lp, cur, crows, w.prop, n, d, dz, done);
 }
 
 template <int PREC>
@@ -444,7 +450,8 @@ void enqueue_step(const MutateArgs& a, const LargeScratch& w, int bm, int s, boo
   const long long nz = (long long)n * (dz / 4);
   z_kernel<PREC><<<(unsigned)((nz + 255) / 256), 256, 0, st>>>(w.z, n, d, dz, a.rows, step,
                                                                a.level, a.level_ptr, a.seed,
-                                                               a.run, a.zsign, a.done_ptr);
+                                                               a.run, a.zsign, w.zsgn,
+                                                               a.done_ptr);
   // current fields: the step-0 source (through its row maps) or the output
   const float* cur = first ? a.src : a.dst;
   const int32_t* crows = first ? (a.src_rows ? a.src_rows : a.rows) : a.rows;
@@ -568,7 +575,8 @@ int large_dz(int d) { return (d + 63) / 64 * 64; }
 size_t large_scratch_bytes(int n, int d) {
   const size_t dz = (size_t)large_dz(d);
   return (size_t)n * dz * sizeof(float) + (size_t)n * d * sizeof(float) +
-         (size_t)n * sizeof(int32_t) + dz * dz * sizeof(float) + 4 * 256;
+         (size_t)n * sizeof(int32_t) + dz * dz * sizeof(float) +
+         (size_t)n * sizeof(unsigned short) + 5 * 256;
 }
 
 LargeScratch large_scratch(void* base, int n, int d) {
@@ -584,6 +592,7 @@ LargeScratch large_scratch(void* base, int n, int d) {
   w.prop = reinterpret_cast<float*>(take((size_t)n * d * sizeof(float)));
   w.accp = reinterpret_cast<int32_t*>(take((size_t)n * sizeof(int32_t)));
   w.lp = take(dz * dz * sizeof(float));
+  w.zsgn = reinterpret_cast<unsigned short*>(take((size_t)n * sizeof(unsigned short)));
   return w;
 }
 

@@ -23,10 +23,12 @@
 // matrix cores work on step s; a step needs two workgroup barriers.
 //
 // Symmetry: the float32 product (four MFMA chains over interleaved K, added
-// at the end) is odd in z by IEEE rounding.  The 16-bit
-// matrix instructions round their internal sums in a way that is not odd,
-// so the 16-bit increment is formed as (M(z) - M(-z)) / 2, which is odd by
-// construction; with the symmetric normals the proposal law is exactly
+// at the end) is odd in z by IEEE rounding.  The 16-bit matrix instructions
+// round their internal sums in a way that is not odd, so the 16-bit
+// increment is formed as s M(s z), with s the sign of the particle's first
+// normal (row p enters with its sign bits flipped when s = -1, exactly):
+// negating z flips s, so the increment is odd in z bit for bit at the cost
+// of one product; with the symmetric normals the proposal law is exactly
 // symmetric, so the Metropolis ratio needs no Hastings term.
 #include <type_traits>
 
@@ -267,6 +269,10 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
     const int cb = s & 1;
     // ---- proposal phi' = phi + Bt^T z for the owned column blocks (MFMA)
     f32x4 acc[NBW], accn[NBW], acc2[NBW], acc3[NBW];  // float32: four independent chains
+    // 16-bit forms: sign bit of the first normal of this lane's A row
+    unsigned short rsgn = 0;
+    if constexpr (!F32)
+      rsgn = reinterpret_cast<const unsigned short*>(&zs[cb][p * ZS])[0] & 0x8000u;
 #pragma unroll
     for (int j = 0; j < NBW; ++j) {
       const int nb = nbs[j];
@@ -284,24 +290,17 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
           }
         } else {
           if (2 * t <= nb) {
-            const u16x8 za = *reinterpret_cast<const u16x8*>(&zs[cb][p * ZS + 32 * t + 8 * g]);
-            const u16x8 zn = za ^ (unsigned short)0x8000u;   // -z, exact
+            const u16x8 za =
+                *reinterpret_cast<const u16x8*>(&zs[cb][p * ZS + 32 * t + 8 * g]) ^ rsgn;
             const FragT b = bfr[C::OFF(j) + t];
-            if constexpr (C::PREC == PHI4_BF16) {
+            if constexpr (C::PREC == PHI4_BF16)
               acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, za),
                                                                __builtin_bit_cast(bf16x8, b),
                                                                acc[j], 0, 0, 0);
-              accn[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, zn),
-                                                                __builtin_bit_cast(bf16x8, b),
-                                                                accn[j], 0, 0, 0);
-            } else {
+            else
               acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, za),
                                                               __builtin_bit_cast(f16x8, b),
                                                               acc[j], 0, 0, 0);
-              accn[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, zn),
-                                                               __builtin_bit_cast(f16x8, b),
-                                                               accn[j], 0, 0, 0);
-            }
           }
         }
       }
@@ -314,12 +313,19 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
       draw_normals(cb ^ 1, (uint32_t)(a.step0 + s + 1));
     }
 
+    // 16-bit forms: signs of the rows of this lane's outputs (rows 4g + jj)
+    bool oneg[4] = {false, false, false, false};
+    if constexpr (!F32) {
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj)
+        oneg[jj] = reinterpret_cast<const unsigned short*>(&zs[cb][(4 * g + jj) * ZS])[0] & 0x8000u;
+    }
 #pragma unroll
     for (int j = 0; j < NBW; ++j)
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) {
         const float inc = F32 ? (acc[j][jj] + accn[j][jj]) + (acc2[j][jj] + acc3[j][jj])
-                              : 0.5f * (acc[j][jj] - accn[j][jj]);
+                              : (oneg[jj] ? -acc[j][jj] : acc[j][jj]);
         pn[j][jj] = ph[j][jj] + inc;
       }
 
