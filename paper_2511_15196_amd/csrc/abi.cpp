@@ -934,9 +934,20 @@ int phi4_observables(void* handle, double* out) {
   return PHI4_OK;
 }
 
-int phi4_tile_choice(int32_t n, int32_t d, int32_t precision, int32_t* rows_host) {
-  if (!rows_host) return fail(PHI4_EINVAL, "phi4_tile_choice: NULL output");
-  *rows_host = large_tile_choice(n, d, precision);
+int phi4_tile_choice(int32_t n, int32_t d, int32_t precision, int32_t* rows_host,
+                     int32_t* cols_host) {
+  if (!rows_host || !cols_host) return fail(PHI4_EINVAL, "phi4_tile_choice: NULL output");
+  int cols = 0;
+  *rows_host = large_tile_choice(n, d, precision, &cols);
+  *cols_host = cols;
+  return PHI4_OK;
+}
+
+int phi4_set_tile(int32_t n, int32_t d, int32_t precision, int32_t rows, int32_t cols) {
+  if (n < 1 || d < 1 || d > PHI4_MAX_SITES || !mutate_supported(d, precision))
+    return fail(PHI4_EINVAL, "phi4_set_tile: bad shape or precision");
+  if (!large_set_tile(n, d, precision, rows, cols))
+    return fail(PHI4_EINVAL, "phi4_set_tile: tile must be 32x64, 64x64, 128x64 or 128x128");
   return PHI4_OK;
 }
 

@@ -120,11 +120,12 @@ __global__ __launch_bounds__(256) void lp_kernel(const float* __restrict__ Bt, i
 
 // phi'[p][c] = phi[irow(p)][c] + sum_{k <= c} z[p][k] Lp[c][k].
 //
-// Workgroup tile BM particles x 64 columns, 4 waves as 2 x 2 (each BM/2 x 32
-// as 16 x 16 MFMA fragments), K in tiles of 64 through double-buffered LDS
-// (row stride padded by one 16-byte vector); global loads run two K tiles
-// ahead in two register sets, so that a load has two tiles of MFMA work to
-// land.  Column tiles are taken in pairs (x, J - 1 - x): tile j of the
+// Workgroup tile BM particles x BN columns, 4 waves as 2 x 2 (each
+// BM/2 x BN/2 as 16 x 16 MFMA fragments), K in tiles of 64 through
+// double-buffered LDS (row stride padded by one 16-byte vector); global
+// loads run S K tiles ahead in S register stages, so that a load has S tiles
+// of MFMA work to land (S = 4 for the 16-bit 128 x 128 tile, whose K tiles
+// are short in MFMA time, else 2).  Column tiles are taken in pairs (x, J - 1 - x): tile j of the
 // triangular product has j + 1 K tiles, so every pair costs the same.
 //
 // float32 form: lane (p, g) of 16x16x4 step m supplies A[p][k], B[k][p] with
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(256) void lp_kernel(const float* __restrict__ Bt, i
 // result is multiplied by s: the increment s M(s z) is odd in z bit for bit
 // (negating z flips s), which the rounding inside the 16-bit dot products
 // alone does not guarantee.
-template <int PREC, int BM>
+template <int PREC, int BM, int BN, int S>
 __global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
                                                    const unsigned short* __restrict__ zsgn,
                                                    const void* __restrict__ lpin,
@@ -146,7 +147,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
   if (done && *done) return;
   constexpr bool F32 = PREC == PHI4_FP32;
   using T = typename std::conditional<F32, float, unsigned short>::type;
-  constexpr int BN = 64, BK = 64;
+  constexpr int BK = 64;
   constexpr int EPV = 16 / (int)sizeof(T);     // elements per 16-byte vector
   constexpr int VPR = BK / EPV;                // vectors per tile row
   constexpr int KS = BK + EPV;                 // LDS row stride (elements)
@@ -165,7 +166,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
   const T* z = static_cast<const T*>(zin);
   const T* lp = static_cast<const T*>(lpin);
 
-  u32x4 ra0[AV], rb0[BV], ra1[AV], rb1[BV];
+  static_assert(S % 2 == 0, "register stages pair with the two LDS buffers");
+  u32x4 ra[S][AV], rb[S][BV];   // register stages: tile t waits in stage t % S
   // 16-bit forms: sign masks of this thread's A rows (both halves of a word)
   unsigned int amask[AV];
 #pragma unroll
@@ -215,7 +217,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
 #pragma unroll
         for (int j = 0; j < FN; ++j)
           bf[j] = *reinterpret_cast<const float4*>(
-              &Bs[buf][(wc * 32 + 16 * j + pl) * KS + 16 * kc + 4 * gl]);
+              &Bs[buf][(wc * (BN / 2) + 16 * j + pl) * KS + 16 * kc + 4 * gl]);
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -237,7 +239,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
 #pragma unroll
         for (int j = 0; j < FN; ++j)
           bf[j] = *reinterpret_cast<const u16x8*>(
-              &Bs[buf][(wc * 32 + 16 * j + pl) * KS + 32 * kc + 8 * gl]);
+              &Bs[buf][(wc * (BN / 2) + 16 * j + pl) * KS + 32 * kc + 8 * gl]);
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -262,35 +264,59 @@ __global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
     for (int i = 0; i < FM; ++i)
 #pragma unroll
       for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    gload(ra0, rb0, c0, 0);
-    sstore(ra0, rb0, 0);
-    if (nkt > 1) gload(ra1, rb1, c0, 1);
+    // tile 0 into LDS buffer 0, tiles 1 .. S in flight (tile S reuses stage 0)
+    gload(ra[0], rb[0], c0, 0);
+    sstore(ra[0], rb[0], 0);
+#pragma unroll
+    for (int u = 1; u <= S; ++u)
+      if (u < nkt) gload(ra[u % S], rb[u % S], c0, u);
     __syncthreads();
-    for (int kt = 0; kt < nkt; kt += 2) {
-      if (kt + 2 < nkt) gload(ra0, rb0, c0, kt + 2);
-      compute(0);
-      if (kt + 1 < nkt) sstore(ra1, rb1, 1);
-      __syncthreads();
-      if (kt + 1 >= nkt) break;
-      if (kt + 3 < nkt) gload(ra1, rb1, c0, kt + 3);
-      compute(1);
-      if (kt + 2 < nkt) sstore(ra0, rb0, 0);
-      __syncthreads();
+    // tile kt is multiplied from LDS buffer kt & 1 while tiles kt+1 .. kt+S
+    // are in flight; a load has S tiles of work to land
+    for (int kt0 = 0; kt0 < nkt; kt0 += S) {
+#pragma unroll
+      for (int u = 0; u < S; ++u) {
+        const int kt = kt0 + u;
+        if (kt < nkt) {
+          compute(u & 1);
+          if (kt + 1 < nkt) sstore(ra[(u + 1) % S], rb[(u + 1) % S], (u + 1) & 1);
+          __syncthreads();
+          if (kt + 1 + S < nkt) gload(ra[(u + 1) % S], rb[(u + 1) % S], c0, kt + 1 + S);
+        }
+      }
     }
-    // epilogue: result item r of lane (p, g) is row 4g + r, column p
+    // epilogue: result item r of lane (p, g) is row 4g + r, column p.  All
+    // loads first (clamped addresses, no branches), so that they overlap;
+    // then the masked stores.
+    int irw[FM][4];
+    bool neg[FM][4];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int pc = min(p0 + wr * (BM / 2) + 16 * i + 4 * gl + r, n - 1);
+        irw[i][r] = irows ? irows[pc] : pc;
+        neg[i][r] = !F32 && zsgn[pc] != 0;
+      }
+    float old[FM][FN][4];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
-        const int c = c0 + wc * 32 + 16 * j + pl;
+        const int cc = min(c0 + wc * (BN / 2) + 16 * j + pl, d - 1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) old[i][j][r] = phi[(size_t)irw[i][r] * d + cc];
+      }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int c = c0 + wc * (BN / 2) + 16 * j + pl;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int p = p0 + wr * (BM / 2) + 16 * i + 4 * gl + r;
-          if (p < n && c < d) {
-            const float inc = (F32 || !zsgn[p]) ? acc[i][j][r] : -acc[i][j][r];
-            const int ir = irows ? irows[p] : p;
-            prop[(size_t)p * d + c] = phi[(size_t)ir * d + c] + inc;
-          }
+          if (p < n && c < d)
+            prop[(size_t)p * d + c] = old[i][j][r] + (neg[i][r] ? -acc[i][j][r] : acc[i][j][r]);
         }
       }
   }
@@ -428,22 +454,38 @@ __global__ void clear_i32_kernel(int32_t* x, int n) {
   if (i < n) x[i] = 0;
 }
 
+// Proposal-product tiles the tuner chooses from (particles x columns).
+constexpr int kTiles[4][2] = {{32, 64}, {64, 64}, {128, 64}, {128, 128}};
+
 template <int PREC>
-void launch_gemm(int bm, const LargeScratch& w, const float* cur, const int32_t* crows, int n,
+void launch_gemm(int tile, const LargeScratch& w, const float* cur, const int32_t* crows, int n,
                  int d, const int32_t* done, hipStream_t st) {
   const int dz = large_dz(d);
-  const int J = (d + 63) / 64;
+  const int bm = kTiles[tile][0], bn = kTiles[tile][1];
+  const int J = (d + bn - 1) / bn;
   const dim3 grid((unsigned)((J + 1) / 2), (unsigned)((n + bm - 1) / bm));
-  if (bm == 32)
-    gemm_kernel<PREC, 32><<<grid, 256, 0, st>>>(w.z, w.zsgn, w.lp, cur, crows, w.prop, n, d, dz, done);
-  else if (bm == 128)
-    gemm_kernel<PREC, 128><<<grid, 256, 0, st>>>(w.z, w.zsgn, w.lp, cur, crows, w.prop, n, d, dz, done);
-  else
-    gemm_kernel<PREC, 64><<<grid, 256, 0, st>>>(w.z, w.zsgn, w.lp, cur, crows, w.prop, n, d, dz, done);
+  switch (tile) {
+    case 0:
+      gemm_kernel<PREC, 32, 64, 2><<<grid, 256, 0, st>>>(w.z, w.zsgn, w.lp, cur, crows, w.prop, n, d,
+                                                      dz, done);
+      break;
+    case 2:
+      gemm_kernel<PREC, 128, 64, 2><<<grid, 256, 0, st>>>(w.z, w.zsgn, w.lp, cur, crows, w.prop, n, d,
+                                                       dz, done);
+      break;
+    case 3:
+      gemm_kernel<PREC, 128, 128, PREC == PHI4_FP32 ? 2 : 4><<<grid, 256, 0, st>>>(w.z, w.zsgn, w.lp, cur, crows, w.prop, n,
+                                                        d, dz, done);
+      break;
+    default:
+      gemm_kernel<PREC, 64, 64, 2><<<grid, 256, 0, st>>>(w.z, w.zsgn, w.lp, cur, crows, w.prop, n, d,
+                                                      dz, done);
+      break;
+  }
 }
 
 template <int PREC>
-void enqueue_step(const MutateArgs& a, const LargeScratch& w, int bm, int s, bool first,
+void enqueue_step(const MutateArgs& a, const LargeScratch& w, int tile, int s, bool first,
                   hipStream_t st) {
   const int n = a.n, d = a.d, dz = large_dz(d);
   const uint32_t step = (uint32_t)(a.step0 + s);
@@ -455,7 +497,7 @@ void enqueue_step(const MutateArgs& a, const LargeScratch& w, int bm, int s, boo
   // current fields: the step-0 source (through its row maps) or the output
   const float* cur = first ? a.src : a.dst;
   const int32_t* crows = first ? (a.src_rows ? a.src_rows : a.rows) : a.rows;
-  launch_gemm<PREC>(bm, w, cur, crows, n, d, a.done_ptr, st);
+  launch_gemm<PREC>(tile, w, cur, crows, n, d, a.done_ptr, st);
   AcceptArgs aa = {};
   aa.cur = cur;
   aa.crows = crows;
@@ -491,13 +533,11 @@ void enqueue_step(const MutateArgs& a, const LargeScratch& w, int bm, int s, boo
     accept_kernel<false><<<n, kAT, lds, st>>>(aa);
 }
 
-constexpr int kTileChoices[3] = {32, 64, 128};
-
-// Particle-tile height of the proposal product per (device, n, d, precision):
-// timed once per shape on the caller's stream (hipEvents, three launches of
-// each choice after one warm-up) and kept for the process.  Inside a stream
-// capture nothing can be timed; the choice is then the largest height that
-// still gives every compute unit two workgroups, and it is not kept.
+// Proposal-product tile per (device, n, d, precision): timed once per shape
+// on the caller's stream (hipEvents, three launches of each choice after one
+// warm-up) and kept for the process.  Inside a stream capture nothing can be
+// timed; the choice is then the largest tile that still gives every compute
+// unit two workgroups, and it is not kept.
 struct TileKey {
   int dev, n, d, prec;
   bool operator<(const TileKey& o) const {
@@ -511,10 +551,12 @@ std::mutex g_tile_mu;
 std::map<TileKey, int> g_tiles;
 
 int heuristic_tile(int n, int d) {
-  const int pairs = ((d + 63) / 64 + 1) / 2;
-  for (int bm : {128, 64})
-    if ((long long)pairs * ((n + bm - 1) / bm) >= 512) return bm;
-  return 32;
+  for (int t = 3; t > 0; --t) {
+    const int bm = kTiles[t][0], bn = kTiles[t][1];
+    const long long wgs = (long long)(((d + bn - 1) / bn + 1) / 2) * ((n + bm - 1) / bm);
+    if (wgs >= 512) return t;
+  }
+  return 0;
 }
 
 template <int PREC>
@@ -527,17 +569,17 @@ int tune_tile(const LargeScratch& w, int n, int d, hipStream_t st) {
   }
   int best = heuristic_tile(n, d);
   float best_ms = 1e30f;
-  for (int bm : kTileChoices) {
+  for (int t = 0; t < 4; ++t) {
     // operands: whatever the scratch holds (timing only); prop doubles as phi
-    launch_gemm<PREC>(bm, w, w.prop, nullptr, n, d, nullptr, st);
+    launch_gemm<PREC>(t, w, w.prop, nullptr, n, d, nullptr, st);
     (void)hipEventRecord(e0, st);
-    for (int r = 0; r < 3; ++r) launch_gemm<PREC>(bm, w, w.prop, nullptr, n, d, nullptr, st);
+    for (int r = 0; r < 3; ++r) launch_gemm<PREC>(t, w, w.prop, nullptr, n, d, nullptr, st);
     (void)hipEventRecord(e1, st);
     float ms = 0.f;
     if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
         ms < best_ms) {
       best_ms = ms;
-      best = bm;
+      best = t;
     }
   }
   (void)hipEventDestroy(e0);
@@ -557,15 +599,15 @@ int gemm_tile(const LargeScratch& w, int n, int d, int prec, hipStream_t st) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
     return heuristic_tile(n, d);
-  int bm;
+  int tile;
   switch (prec) {
-    case PHI4_BF16: bm = tune_tile<PHI4_BF16>(w, n, d, st); break;
-    case PHI4_FP16: bm = tune_tile<PHI4_FP16>(w, n, d, st); break;
-    default: bm = tune_tile<PHI4_FP32>(w, n, d, st); break;
+    case PHI4_BF16: tile = tune_tile<PHI4_BF16>(w, n, d, st); break;
+    case PHI4_FP16: tile = tune_tile<PHI4_FP16>(w, n, d, st); break;
+    default: tile = tune_tile<PHI4_FP32>(w, n, d, st); break;
   }
   std::lock_guard<std::mutex> lk(g_tile_mu);
-  g_tiles[key] = bm;
-  return bm;
+  g_tiles[key] = tile;
+  return tile;
 }
 
 }  // namespace
@@ -600,12 +642,30 @@ void launch_large_init(const LargeScratch& w, int n, hipStream_t s) {
   if (n > 0 && w.accp) clear_i32_kernel<<<(n + 255) / 256, 256, 0, s>>>(w.accp, n);
 }
 
-int large_tile_choice(int n, int d, int precision) {
+bool large_set_tile(int n, int d, int precision, int rows, int cols) {
+  for (int t = 0; t < 4; ++t) {
+    if (kTiles[t][0] == rows && kTiles[t][1] == cols) {
+      int dev = 0;
+      (void)hipGetDevice(&dev);
+      std::lock_guard<std::mutex> lk(g_tile_mu);
+      g_tiles[TileKey{dev, n, d, precision}] = t;
+      return true;
+    }
+  }
+  return false;
+}
+
+int large_tile_choice(int n, int d, int precision, int* cols) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   std::lock_guard<std::mutex> lk(g_tile_mu);
   auto it = g_tiles.find(TileKey{dev, n, d, precision});
-  return it == g_tiles.end() ? 0 : it->second;
+  if (it == g_tiles.end()) {
+    if (cols) *cols = 0;
+    return 0;
+  }
+  if (cols) *cols = kTiles[it->second][1];
+  return kTiles[it->second][0];
 }
 
 // One sweep: n_steps steps of normals, proposal and accept.  A sweep of zero
@@ -617,7 +677,7 @@ int launch_mutate_large(const MutateArgs& a, const LargeScratch& w, int precisio
   const int steps = a.n_steps > 0 ? a.n_steps : 1;
   if (precision != PHI4_FP32 && precision != PHI4_BF16 && precision != PHI4_FP16)
     return PHI4_EINVAL;
-  const int bm = gemm_tile(w, a.n, a.d, precision, s);
+  const int tile = gemm_tile(w, a.n, a.d, precision, s);
   {
     const int dz = large_dz(a.d);
     const dim3 g((unsigned)(dz / 32), (unsigned)(dz / 32));
@@ -630,9 +690,9 @@ int launch_mutate_large(const MutateArgs& a, const LargeScratch& w, int precisio
   }
   for (int t = 0; t < steps; ++t) {
     switch (precision) {
-      case PHI4_FP32: enqueue_step<PHI4_FP32>(a, w, bm, t, t == 0, s); break;
-      case PHI4_BF16: enqueue_step<PHI4_BF16>(a, w, bm, t, t == 0, s); break;
-      default: enqueue_step<PHI4_FP16>(a, w, bm, t, t == 0, s); break;
+      case PHI4_FP32: enqueue_step<PHI4_FP32>(a, w, tile, t, t == 0, s); break;
+      case PHI4_BF16: enqueue_step<PHI4_BF16>(a, w, tile, t, t == 0, s); break;
+      default: enqueue_step<PHI4_FP16>(a, w, tile, t, t == 0, s); break;
     }
   }
   if (a.prop && a.n_steps > 0) {

@@ -128,6 +128,38 @@ def test_increment_is_odd_bitwise(precision, L):
     assert np.any(up != 0)
 
 
+TILES = [(32, 64), (64, 64), (128, 64), (128, 128)]
+
+
+@pytest.mark.parametrize("tile", TILES)
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("L,n", [(17, 300), (24, 131)])
+def test_every_product_tile(tile, precision, L, n):
+    """Each tile of the three-pass product, pinned: the product against the
+    float64 product of the same rounded operands, and bitwise oddness."""
+    d = L * L
+    say("tile", tile, precision, L, n)
+    P.phi4_set_tile(n, d, precision, *tile)
+    assert P.phi4_tile_choice(n, d, precision) == tile
+    phi = synth.broken_phase_fields(L + n + 1, n, L)
+    Bt32, B = factor(L, L + 1)
+    r = run_kernel(phi, L, Bt32, precision=precision)
+    z = gpu_normals(5, 1, 3, 2, n, d)
+    zr = oprec.round_operand(z, precision)
+    Br = oprec.round_operand(B, precision)
+    want = phi.astype(np.float64) + zr @ Br.T
+    assert np.all(np.abs(r["prop"] - want) <= product_tolerance(zr, Br, want))
+    zero = np.zeros((n, d), dtype=np.float32)
+    up = run_kernel(zero, L, Bt32, zsign=1.0, precision=precision)["prop"]
+    dn = run_kernel(zero, L, Bt32, zsign=-1.0, precision=precision)["prop"]
+    assert np.array_equal(dn, -up)
+
+
+def test_set_tile_rejects_unknown_tiles():
+    with pytest.raises(P.Phi4Error):
+        P.phi4_set_tile(100, 289, "fp32", 48, 64)
+
+
 def oracle_tempered(phi, prop, beta, L, seed, run, level, step, rows, m2=-4.0, lam=8.0):
     la = osmc.tempered_log_alpha(phi.astype(np.float64), prop.astype(np.float64), beta, L, m2, lam)
     lu = np.log(orng.accept_uniforms(seed, run, level, step, rows))
