@@ -349,46 +349,55 @@ struct AcceptArgs {
   uint8_t* acc_flags;        // optional, per slot (this step)
 };
 
-// Site terms of Sec. 2 Eq. (1) for site x of a row staged in LDS.
-__device__ __forceinline__ float site_term(const float* f, int x, int L, int d, float m2,
-                                           float lam, float& f2) {
-  const int x1 = x % L;
-  const int y1 = x - x1 + (x1 + 1 == L ? 0 : x1 + 1);
-  const int y0 = x + L < d ? x + L : x + L - d;
-  const float v = f[x];
-  const float a1 = f[y1] - v, a0 = f[y0] - v;
-  f2 = v * v;
-  return 0.5f * (a1 * a1 + a0 * a0) + 0.5f * m2 * f2 + lam * f2 * f2;
-}
-
-template <bool CONSTRAINED>
+template <bool CONSTRAINED, int PER>   // PER >= d / kAT sites per thread
 __global__ __launch_bounds__(kAT) void accept_kernel(AcceptArgs a) {
-  extern __shared__ float rowbuf[];   // 2 d floats: phi, phi'
+  extern __shared__ __align__(16) float rowbuf[];   // d pairs (phi, phi')
   __shared__ float red[kAT / 64][6];
   __shared__ int dec;
   const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int d = a.d, L = a.L;
   const int cr = a.crows ? a.crows[p] : p;
   const int orw = a.orows ? a.orows[p] : p;
-  float* fo = rowbuf;
-  float* fn = rowbuf + d;
-  for (int x = tid; x < d; x += kAT) {
-    fo[x] = a.cur[(size_t)cr * d + x];
-    fn[x] = a.prop[(size_t)p * d + x];
+  float2* f = reinterpret_cast<float2*>(rowbuf);
+  {
+    // every load of this thread in flight before the first LDS store
+    const float* cp = a.cur + (size_t)cr * d;
+    const float* pp = a.prop + (size_t)p * d;
+    float vo[PER], vn[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int x = min(tid + i * kAT, d - 1);
+      vo[i] = cp[x];
+      vn[i] = pp[x];
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i)
+      if (tid + i * kAT < d) f[tid + i * kAT] = make_float2(vo[i], vn[i]);
   }
   __syncthreads();
-  // S(phi), S(phi'), sum of per-site differences, dU0, M(phi), M(phi')
+  // S(phi), S(phi'), sum of per-site differences, dU0, M(phi), M(phi');
+  // neighbours x + e1 (wrapping within the row) and x + e0 (wrapping over
+  // the lattice), one 8-byte LDS read per site for both fields
   float so = 0.f, sn = 0.f, ds = 0.f, du = 0.f, mo = 0.f, mn = 0.f;
+  const int cstep = kAT % L;
+  int col = tid % L;
+  const float hm2 = 0.5f * a.m2, lam = a.lam;
   for (int x = tid; x < d; x += kAT) {
-    float f2o, f2n;
-    const float to = site_term(fo, x, L, d, a.m2, a.lam, f2o);
-    const float tn = site_term(fn, x, L, d, a.m2, a.lam, f2n);
+    const int y1 = col + 1 == L ? x + 1 - L : x + 1;
+    const int y0 = x + L < d ? x + L : x + L - d;
+    const float2 v = f[x], r1 = f[y1], r0 = f[y0];
+    const float a1o = r1.x - v.x, a0o = r0.x - v.x, f2o = v.x * v.x;
+    const float a1n = r1.y - v.y, a0n = r0.y - v.y, f2n = v.y * v.y;
+    const float to = 0.5f * (a1o * a1o + a0o * a0o) + hm2 * f2o + lam * f2o * f2o;
+    const float tn = 0.5f * (a1n * a1n + a0n * a0n) + hm2 * f2n + lam * f2n * f2n;
     so += to;
     sn += tn;
     ds += tn - to;
     du += 0.5f * (f2n - f2o);
-    mo += fo[x];
-    mn += fn[x];
+    mo += v.x;
+    mn += v.y;
+    col += cstep;
+    if (col >= L) col -= L;
   }
   float v[6] = {so, sn, ds, du, mo, mn};
 #pragma unroll
@@ -425,8 +434,8 @@ __global__ __launch_bounds__(kAT) void accept_kernel(AcceptArgs a) {
   }
   __syncthreads();
   if (dec || a.copy_rejected) {
-    const float* srow = dec ? fn : fo;
-    for (int x = tid; x < d; x += kAT) a.dst[(size_t)orw * d + x] = srow[x];
+    const bool take_new = dec;
+    for (int x = tid; x < d; x += kAT) a.dst[(size_t)orw * d + x] = take_new ? f[x].y : f[x].x;
   }
 }
 
@@ -484,6 +493,19 @@ void launch_gemm(int tile, const LargeScratch& w, const float* cur, const int32_
   }
 }
 
+template <bool CONSTRAINED>
+void launch_accept(int per, int n, size_t lds, const AcceptArgs& aa, hipStream_t st) {
+  static_assert(PHI4_MAX_SITES <= 16 * kAT, "accept stages at most 16 sites per thread");
+  if (per <= 2)
+    accept_kernel<CONSTRAINED, 2><<<n, kAT, lds, st>>>(aa);
+  else if (per <= 4)
+    accept_kernel<CONSTRAINED, 4><<<n, kAT, lds, st>>>(aa);
+  else if (per <= 8)
+    accept_kernel<CONSTRAINED, 8><<<n, kAT, lds, st>>>(aa);
+  else
+    accept_kernel<CONSTRAINED, 16><<<n, kAT, lds, st>>>(aa);
+}
+
 template <int PREC>
 void enqueue_step(const MutateArgs& a, const LargeScratch& w, int tile, int s, bool first,
                   hipStream_t st) {
@@ -527,10 +549,11 @@ void enqueue_step(const MutateArgs& a, const LargeScratch& w, int tile, int s, b
   aa.accp = w.accp;
   aa.acc_flags = (s == a.n_steps - 1) ? a.acc_flags : nullptr;
   const size_t lds = 2 * (size_t)d * sizeof(float);
+  const int per = (d + kAT - 1) / kAT;
   if (a.kind == 1)
-    accept_kernel<true><<<n, kAT, lds, st>>>(aa);
+    launch_accept<true>(per, n, lds, aa, st);
   else
-    accept_kernel<false><<<n, kAT, lds, st>>>(aa);
+    launch_accept<false>(per, n, lds, aa, st);
 }
 
 // Proposal-product tile per (device, n, d, precision): timed once per shape
