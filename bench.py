@@ -40,9 +40,9 @@ VALU_PEAK = 256 * 4 * 16 * 2.4e9
 # counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0: the factors that make a
 # 256 MiB device-to-device copy read and write 256 MiB on the same counters),
 # valid only for the kernel sources they were taken on.
-TRAFFIC = dict(bytes_per_launch=(517.48 * 1.99983 + 1072.0) * 1024,
-               sources={"k_mutate.hip": "465e716a1e2bc9b9717a2032a856dd850a4dbd3a6daaf2735f3d5cb52bb5dbd7",
-                        "common.hpp": "4b8e9970df8aa2e23ccc28d4b942b11777cc1a6942cb635f059822ebb0d416a7"})
+TRAFFIC = dict(bytes_per_launch=(516.40 * 1.99980 + 1072.0) * 1024,
+               sources={"k_mutate.hip": "9d73ba65343919455708a3e7da700cc69f132734f4ba260e38d111557c397d9c",
+                        "common.hpp": "358094e7cd9e45b5e8f59514c842bf83ba930c10b9e38d461d9bf97c55e9cad7"})
 
 
 def traffic_per_launch():

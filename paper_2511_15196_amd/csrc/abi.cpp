@@ -167,7 +167,8 @@ struct Handle {
   int32_t* nbstatus;
   double* nbscr;
   // host mirrors
-  void* pinned;  // two state copies
+  void* pinned;      // two state copies
+  void* pinned_dev;  // the same memory as the device addresses it
   hipEvent_t ev[2];
   // kernel timing
   bool timing;
@@ -239,10 +240,11 @@ int settle(Handle* h) {
 
 // Reweighting, resampling ancestors, and the covariance factor of the
 // resampled population (read through the ancestors; nothing is copied).
-int enqueue_reweight(Handle* h) {
+int enqueue_reweight(Handle* h, SmcState* mirror = nullptr) {
   SmcBufs& b = h->sb;
   materialize(h);
   ReweightArgs ra = {};
+  ra.mirror = mirror;
   ra.S = cur_S(h);
   ra.n = h->n;
   ra.st = b.st;
@@ -322,6 +324,7 @@ Handle* as_handle(void* p, int kind) {
 
 int alloc_pinned(Handle* h, size_t bytes) {
   HIP_TRY(hipHostMalloc(&h->pinned, 2 * bytes, hipHostMallocDefault));
+  HIP_TRY(hipHostGetDevicePointer(&h->pinned_dev, h->pinned, 0));
   HIP_TRY(hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming));
   return PHI4_OK;
@@ -579,12 +582,12 @@ int smc_run(void* handle, int32_t max_levels, int32_t* levels_host) {
   // after the final sweep finds beta = 1 and does nothing.
   int rc = PHI4_OK;
   bool finished = false;
+  SmcState* slots_dev = static_cast<SmcState*>(h->pinned_dev);
   for (int t = 0; t < max_levels && !finished; ++t) {
-    rc = enqueue_reweight(h);
+    // the reweight kernel writes the state after its reweight into slot t & 1
+    rc = enqueue_reweight(h, &slots_dev[t & 1]);
     if (!rc) rc = enqueue_mutate(h);
     if (rc) return rc;
-    HIP_TRY(hipMemcpyAsync(&slots[t & 1], h->sb.st, sizeof(SmcState), hipMemcpyDeviceToHost,
-                           h->stream));
     HIP_TRY(hipEventRecord(h->ev[t & 1], h->stream));
     if (t >= 1) {
       HIP_TRY(hipEventSynchronize(h->ev[(t - 1) & 1]));

@@ -330,6 +330,7 @@ struct ReweightArgs {
   unsigned long long* cdf; // n
   int32_t* marks;          // n
   int32_t* anc;            // n
+  SmcState* mirror;        // optional host-mapped copy of the state after the reweight
 };
 void launch_reweight(const ReweightArgs& a, hipStream_t s);
 void launch_resample_weights(const double* w, int n, uint32_t U, unsigned long long* cdf,

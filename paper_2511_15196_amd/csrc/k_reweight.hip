@@ -442,7 +442,7 @@ __device__ bool reweight_prologue(const ReweightArgs& a, double& beta, double& e
 // Register path, n <= 512 SEG: thread t holds the actions of particles
 // [t per, t per + per), per = ceil(n / 512), for the whole launch.
 template <int SEG>
-__global__ __launch_bounds__(kRT) void reweight_kernel(ReweightArgs a) {
+__device__ __forceinline__ void reweight_impl(const ReweightArgs& a) {
   __shared__ double shd[2 * 4 * kNW];
   __shared__ float shf[2 * 4 * kNW];
   __shared__ unsigned long long shu[kNW];
@@ -561,7 +561,7 @@ __device__ double solve_dbeta(SGet sget, int n, double room, double target, doub
 }
 
 // Large-N variant: actions and weights stay in global memory.
-__global__ __launch_bounds__(kRT) void reweight_global_kernel(ReweightArgs a) {
+__device__ __forceinline__ void reweight_global_impl(const ReweightArgs& a) {
   __shared__ double shd[4 * kNW];
   __shared__ unsigned long long shu[kNW];
   __shared__ int shi[kNW];
@@ -693,6 +693,23 @@ __global__ __launch_bounds__(64) void batch_status_kernel(const SmcState* const*
   b.err = s->err;
   b.pad = 0;
   out[r] = b;
+}
+
+// Thread 0 wrote every field of the run state, so it can publish the state
+// to the host mirror right after the reweight without a barrier.
+__device__ __forceinline__ void publish_state(const ReweightArgs& a) {
+  if (a.mirror && a.st && threadIdx.x == 0) *a.mirror = *a.st;
+}
+
+template <int SEG>
+__global__ __launch_bounds__(kRT) void reweight_kernel(ReweightArgs a) {
+  reweight_impl<SEG>(a);
+  publish_state(a);
+}
+
+__global__ __launch_bounds__(kRT) void reweight_global_kernel(ReweightArgs a) {
+  reweight_global_impl(a);
+  publish_state(a);
 }
 
 }  // namespace

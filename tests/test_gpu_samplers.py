@@ -48,6 +48,20 @@ def test_smc_small_coupled_to_oracle(seed):
     assert abs(g["mean_abs_m"] - o["mean_abs_m"]) < 0.01
 
 
+@pytest.mark.parametrize("seed", [0, 1])
+def test_smc_paper_settings_coupled_to_oracle(seed):
+    """The paper's own settings (m0^2 = -4, lambda = 1, ESS 0.9, 3V steps per
+    level; App. A) on a 4 x 4 lattice, coupled to the oracle's streams."""
+    say("smc paper settings L=4 N=512 seed", seed)
+    g = gpu_smc(4, 512, -4.0, 1.0, 0.9, 48, seed)
+    o = osmc.smc_run(4, -4.0, 1.0, 512, 0.9, 48, seed=seed)
+    say("gpu", g, "oracle", o["logz"], o["n_levels"], o["mean_abs_m"])
+    assert g["rc"] == P.PHI4_DONE
+    assert abs(g["levels"] - o["n_levels"]) <= 1
+    assert abs(g["logz"] - o["logz"]) < 0.1
+    assert abs(g["mean_abs_m"] - o["mean_abs_m"]) < 0.02
+
+
 def test_smc_free_2x2_exact():
     zs = [gpu_smc(2, 4096, 1.0, 0.0, 0.5, 20, s)["logz"] for s in range(8)]
     m, se = np.mean(zs), np.std(zs, ddof=1) / math.sqrt(len(zs))
