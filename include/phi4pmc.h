@@ -221,18 +221,20 @@ int phi4_set_sweep(void* handle, int32_t form);
 
 /* Tile of the three-pass proposal product (autotuned).  The first sweep of a
  * shape (n particles, d sites, precision) on a device times each workgroup
- * tile (32 x 64, 64 x 64, 128 x 64 and 128 x 128 particles x columns) on the
- * caller's stream and keeps the fastest for the process.  *rows_host and
- * *cols_host receive the tile chosen for the current device, or 0 if that
+ * tile (particles x columns x threads: 32 x 64, 64 x 64, 128 x 64 and
+ * 128 x 128 with 256 threads, 128 x 128 with 512) on the caller's stream and
+ * keeps the fastest for the process.  *rows_host, *cols_host and
+ * *threads_host receive the tile chosen for the current device, or 0 if that
  * shape has not run yet.  Host-only, never fails for valid pointers. */
 int phi4_tile_choice(int32_t n, int32_t d, int32_t precision, int32_t* rows_host,
-                     int32_t* cols_host);
+                     int32_t* cols_host, int32_t* threads_host);
 
 /* Pins the proposal-product tile of a shape on the current device instead of
- * timing it (rows x cols one of 32 x 64, 64 x 64, 128 x 64, 128 x 128): for
- * reproducible launches and for tests of every tile.  PHI4_EINVAL for another
- * tile or a bad shape.  Host-only. */
-int phi4_set_tile(int32_t n, int32_t d, int32_t precision, int32_t rows, int32_t cols);
+ * timing it (one of the tiles above): for reproducible launches and for
+ * tests of every tile.  PHI4_EINVAL for another tile or a bad shape.
+ * Host-only. */
+int phi4_set_tile(int32_t n, int32_t d, int32_t precision, int32_t rows, int32_t cols,
+                  int32_t threads);
 
 /* Kernel timing: while enabled, every mutation launch of
  * smc_mutate / smc_run / ns_step is bracketed by HIP events on the handle's

@@ -142,15 +142,16 @@ SWEEPS = {"auto": 0, "fused": 1, "passes": 2}
 
 
 def phi4_tile_choice(n, d, precision="fp32"):
-    """(particles, columns) of the tuned proposal-product tile, (0, 0) if untimed."""
-    rows, cols = ctypes.c_int32(0), ctypes.c_int32(0)
+    """(particles, columns, threads) of the tuned proposal-product tile, zeros if untimed."""
+    rows, cols, threads = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
     _check(lib().phi4_tile_choice(n, d, PRECISIONS[precision], ctypes.byref(rows),
-                                  ctypes.byref(cols)), "phi4_tile_choice")
-    return rows.value, cols.value
+                                  ctypes.byref(cols), ctypes.byref(threads)), "phi4_tile_choice")
+    return rows.value, cols.value, threads.value
 
 
-def phi4_set_tile(n, d, precision, rows, cols):
-    _check(lib().phi4_set_tile(n, d, PRECISIONS[precision], rows, cols), "phi4_set_tile")
+def phi4_set_tile(n, d, precision, rows, cols, threads=256):
+    _check(lib().phi4_set_tile(n, d, PRECISIONS[precision], rows, cols, threads),
+           "phi4_set_tile")
 
 
 def phi4_set_sweep(h, form="auto"):

@@ -78,8 +78,9 @@ SIGNATURES = {
     "smc_batch_run": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), _I32, _I32,
                                      ctypes.POINTER(ctypes.c_int32), _V]),
     "phi4_tile_choice": (ctypes.c_int, [_I32, _I32, _I32, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_int32)]),
-    "phi4_set_tile": (ctypes.c_int, [_I32, _I32, _I32, _I32, _I32]),
+    "phi4_set_tile": (ctypes.c_int, [_I32, _I32, _I32, _I32, _I32, _I32]),
     "phi4_kernel_time": (ctypes.c_int, [_V, _PD, _PI]),
     "phi4_destroy": (ctypes.c_int, [_V]),
     "phi4_last_error": (ctypes.c_char_p, []),

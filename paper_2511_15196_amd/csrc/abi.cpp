@@ -938,19 +938,23 @@ int phi4_observables(void* handle, double* out) {
 }
 
 int phi4_tile_choice(int32_t n, int32_t d, int32_t precision, int32_t* rows_host,
-                     int32_t* cols_host) {
-  if (!rows_host || !cols_host) return fail(PHI4_EINVAL, "phi4_tile_choice: NULL output");
-  int cols = 0;
-  *rows_host = large_tile_choice(n, d, precision, &cols);
+                     int32_t* cols_host, int32_t* threads_host) {
+  if (!rows_host || !cols_host || !threads_host)
+    return fail(PHI4_EINVAL, "phi4_tile_choice: NULL output");
+  int cols = 0, threads = 0;
+  *rows_host = large_tile_choice(n, d, precision, &cols, &threads);
   *cols_host = cols;
+  *threads_host = threads;
   return PHI4_OK;
 }
 
-int phi4_set_tile(int32_t n, int32_t d, int32_t precision, int32_t rows, int32_t cols) {
+int phi4_set_tile(int32_t n, int32_t d, int32_t precision, int32_t rows, int32_t cols,
+                  int32_t threads) {
   if (n < 1 || d < 1 || d > PHI4_MAX_SITES || !mutate_supported(d, precision))
     return fail(PHI4_EINVAL, "phi4_set_tile: bad shape or precision");
-  if (!large_set_tile(n, d, precision, rows, cols))
-    return fail(PHI4_EINVAL, "phi4_set_tile: tile must be 32x64, 64x64, 128x64 or 128x128");
+  if (!large_set_tile(n, d, precision, rows, cols, threads))
+    return fail(PHI4_EINVAL, "phi4_set_tile: tile must be 32x64, 64x64, 128x64 or 128x128 "
+                             "with 256 threads, or 128x128 with 512");
   return PHI4_OK;
 }
 

@@ -299,11 +299,12 @@ int large_dz(int d);
 size_t large_scratch_bytes(int n, int d);
 LargeScratch large_scratch(void* base, int n, int d);
 void launch_large_init(const LargeScratch& w, int n, hipStream_t s);
-// Tile (particles, and columns into *cols) the proposal product uses at this
-// shape on the current device once it has been timed (0 before).
-int large_tile_choice(int n, int d, int precision, int* cols);
+// Tile (particles; columns and threads into *cols, *threads) the proposal
+// product uses at this shape on the current device once it has been timed
+// (0 before).
+int large_tile_choice(int n, int d, int precision, int* cols, int* threads);
 // Pins the tile of a shape on the current device (false: not a tile choice).
-bool large_set_tile(int n, int d, int precision, int rows, int cols);
+bool large_set_tile(int n, int d, int precision, int rows, int cols, int threads);
 int launch_mutate_large(const MutateArgs& a, const LargeScratch& w, int precision, hipStream_t s);
 
 // k_field.hip

@@ -136,8 +136,8 @@ __global__ __launch_bounds__(256) void lp_kernel(const float* __restrict__ Bt, i
 // result is multiplied by s: the increment s M(s z) is odd in z bit for bit
 // (negating z flips s), which the rounding inside the 16-bit dot products
 // alone does not guarantee.
-template <int PREC, int BM, int BN, int S>
-__global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
+template <int PREC, int BM, int BN, int S, int NT = 256>
+__global__ __launch_bounds__(NT) void gemm_kernel(const void* __restrict__ zin,
                                                    const unsigned short* __restrict__ zsgn,
                                                    const void* __restrict__ lpin,
                                                    const float* __restrict__ phi,
@@ -151,14 +151,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
   constexpr int EPV = 16 / (int)sizeof(T);     // elements per 16-byte vector
   constexpr int VPR = BK / EPV;                // vectors per tile row
   constexpr int KS = BK + EPV;                 // LDS row stride (elements)
-  constexpr int AV = BM * VPR / 256, BV = BN * VPR / 256;
-  static_assert(AV >= 1 && BV >= 1, "tile too small for 256 threads");
-  constexpr int FM = BM / 32, FN = BN / 32;    // fragments per wave
+  constexpr int WC = NT / 128;                 // waves: 2 rows x WC columns
+  constexpr int AV = BM * VPR / NT, BV = BN * VPR / NT;
+  static_assert(AV >= 1 && BV >= 1 && BM * VPR % NT == 0 && BN * VPR % NT == 0,
+                "tile too small for the thread count");
+  constexpr int WM = BM / 2, WN = BN / WC;     // wave tile
+  constexpr int FM = WM / 16, FN = WN / 16;    // fragments per wave
   __shared__ __align__(16) T As[2][BM * KS];
   __shared__ __align__(16) T Bs[2][BN * KS];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int pl = lane & 15, gl = lane >> 4;
-  const int wr = wv >> 1, wc = wv & 1;
+  const int wr = wv / WC, wc = wv % WC;
   const int p0 = blockIdx.y * BM;
   const int J = (d + BN - 1) / BN;
   const int x = blockIdx.x;
@@ -172,7 +175,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
   unsigned int amask[AV];
 #pragma unroll
   for (int i = 0; i < AV; ++i) {
-    const int row = (tid + 256 * i) / VPR;
+    const int row = (tid + NT * i) / VPR;
     const unsigned int m = F32 ? 0u : (unsigned int)zsgn[min(p0 + row, n - 1)];
     amask[i] = m | (m << 16);
   }
@@ -180,13 +183,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
     const int k0 = kt * BK;
 #pragma unroll
     for (int i = 0; i < AV; ++i) {
-      const int v = tid + 256 * i, row = v / VPR, vc = v % VPR;
+      const int v = tid + NT * i, row = v / VPR, vc = v % VPR;
       ra[i] = *reinterpret_cast<const u32x4*>(z + (size_t)min(p0 + row, n - 1) * dz + k0 +
                                               vc * EPV);
     }
 #pragma unroll
     for (int i = 0; i < BV; ++i) {
-      const int v = tid + 256 * i, row = v / VPR, vc = v % VPR;
+      const int v = tid + NT * i, row = v / VPR, vc = v % VPR;
       rb[i] = *reinterpret_cast<const u32x4*>(lp + (size_t)min(c0 + row, dz - 1) * dz + k0 +
                                               vc * EPV);
     }
@@ -194,12 +197,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
   auto sstore = [&](const u32x4(&ra)[AV], const u32x4(&rb)[BV], int buf) __attribute__((always_inline)) {
 #pragma unroll
     for (int i = 0; i < AV; ++i) {
-      const int v = tid + 256 * i, row = v / VPR, vc = v % VPR;
+      const int v = tid + NT * i, row = v / VPR, vc = v % VPR;
       *reinterpret_cast<u32x4*>(&As[buf][row * KS + vc * EPV]) = F32 ? ra[i] : (ra[i] ^ amask[i]);
     }
 #pragma unroll
     for (int i = 0; i < BV; ++i) {
-      const int v = tid + 256 * i, row = v / VPR, vc = v % VPR;
+      const int v = tid + NT * i, row = v / VPR, vc = v % VPR;
       *reinterpret_cast<u32x4*>(&Bs[buf][row * KS + vc * EPV]) = rb[i];
     }
   };
@@ -213,11 +216,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
 #pragma unroll
         for (int i = 0; i < FM; ++i)
           af[i] = *reinterpret_cast<const float4*>(
-              &As[buf][(wr * (BM / 2) + 16 * i + pl) * KS + 16 * kc + 4 * gl]);
+              &As[buf][(wr * WM + 16 * i + pl) * KS + 16 * kc + 4 * gl]);
 #pragma unroll
         for (int j = 0; j < FN; ++j)
           bf[j] = *reinterpret_cast<const float4*>(
-              &Bs[buf][(wc * (BN / 2) + 16 * j + pl) * KS + 16 * kc + 4 * gl]);
+              &Bs[buf][(wc * WN + 16 * j + pl) * KS + 16 * kc + 4 * gl]);
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -235,11 +238,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
 #pragma unroll
         for (int i = 0; i < FM; ++i)
           af[i] = *reinterpret_cast<const u16x8*>(
-              &As[buf][(wr * (BM / 2) + 16 * i + pl) * KS + 32 * kc + 8 * gl]);
+              &As[buf][(wr * WM + 16 * i + pl) * KS + 32 * kc + 8 * gl]);
 #pragma unroll
         for (int j = 0; j < FN; ++j)
           bf[j] = *reinterpret_cast<const u16x8*>(
-              &Bs[buf][(wc * (BN / 2) + 16 * j + pl) * KS + 32 * kc + 8 * gl]);
+              &Bs[buf][(wc * WN + 16 * j + pl) * KS + 32 * kc + 8 * gl]);
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -294,7 +297,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
     for (int i = 0; i < FM; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int pc = min(p0 + wr * (BM / 2) + 16 * i + 4 * gl + r, n - 1);
+        const int pc = min(p0 + wr * WM + 16 * i + 4 * gl + r, n - 1);
         irw[i][r] = irows ? irows[pc] : pc;
         neg[i][r] = !F32 && zsgn[pc] != 0;
       }
@@ -303,7 +306,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
     for (int i = 0; i < FM; ++i)
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
-        const int cc = min(c0 + wc * (BN / 2) + 16 * j + pl, d - 1);
+        const int cc = min(c0 + wc * WN + 16 * j + pl, d - 1);
 #pragma unroll
         for (int r = 0; r < 4; ++r) old[i][j][r] = phi[(size_t)irw[i][r] * d + cc];
       }
@@ -311,10 +314,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(const void* __restrict__ zin,
     for (int i = 0; i < FM; ++i)
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
-        const int c = c0 + wc * (BN / 2) + 16 * j + pl;
+        const int c = c0 + wc * WN + 16 * j + pl;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int p = p0 + wr * (BM / 2) + 16 * i + 4 * gl + r;
+          const int p = p0 + wr * WM + 16 * i + 4 * gl + r;
           if (p < n && c < d)
             prop[(size_t)p * d + c] = old[i][j][r] + (neg[i][r] ? -acc[i][j][r] : acc[i][j][r]);
         }
@@ -463,8 +466,11 @@ __global__ void clear_i32_kernel(int32_t* x, int n) {
   if (i < n) x[i] = 0;
 }
 
-// Proposal-product tiles the tuner chooses from (particles x columns).
-constexpr int kTiles[4][2] = {{32, 64}, {64, 64}, {128, 64}, {128, 128}};
+// Proposal-product tiles the tuner chooses from (particles x columns x
+// threads): the last runs eight waves (2 x 4) for two waves per SIMD.
+constexpr int kNumTiles = 5;
+constexpr int kTiles[kNumTiles][3] = {
+    {32, 64, 256}, {64, 64, 256}, {128, 64, 256}, {128, 128, 256}, {128, 128, 512}};
 
 template <int PREC>
 void launch_gemm(int tile, const LargeScratch& w, const float* cur, const int32_t* crows, int n,
@@ -483,8 +489,12 @@ void launch_gemm(int tile, const LargeScratch& w, const float* cur, const int32_
                                                        dz, done);
       break;
     case 3:
-      gemm_kernel<PREC, 128, 128, PREC == PHI4_FP32 ? 2 : 4><<<grid, 256, 0, st>>>(w.z, w.zsgn, w.lp, cur, crows, w.prop, n,
-                                                        d, dz, done);
+      gemm_kernel<PREC, 128, 128, PREC == PHI4_FP32 ? 2 : 4><<<grid, 256, 0, st>>>(
+          w.z, w.zsgn, w.lp, cur, crows, w.prop, n, d, dz, done);
+      break;
+    case 4:
+      gemm_kernel<PREC, 128, 128, 2, 512><<<grid, 512, 0, st>>>(
+          w.z, w.zsgn, w.lp, cur, crows, w.prop, n, d, dz, done);
       break;
     default:
       gemm_kernel<PREC, 64, 64, 2><<<grid, 256, 0, st>>>(w.z, w.zsgn, w.lp, cur, crows, w.prop, n, d,
@@ -574,7 +584,7 @@ std::mutex g_tile_mu;
 std::map<TileKey, int> g_tiles;
 
 int heuristic_tile(int n, int d) {
-  for (int t = 3; t > 0; --t) {
+  for (int t = 3; t > 0; --t) {   // 256-thread tiles only
     const int bm = kTiles[t][0], bn = kTiles[t][1];
     const long long wgs = (long long)(((d + bn - 1) / bn + 1) / 2) * ((n + bm - 1) / bm);
     if (wgs >= 512) return t;
@@ -592,7 +602,7 @@ int tune_tile(const LargeScratch& w, int n, int d, hipStream_t st) {
   }
   int best = heuristic_tile(n, d);
   float best_ms = 1e30f;
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < kNumTiles; ++t) {
     // operands: whatever the scratch holds (timing only); prop doubles as phi
     launch_gemm<PREC>(t, w, w.prop, nullptr, n, d, nullptr, st);
     (void)hipEventRecord(e0, st);
@@ -665,9 +675,9 @@ void launch_large_init(const LargeScratch& w, int n, hipStream_t s) {
   if (n > 0 && w.accp) clear_i32_kernel<<<(n + 255) / 256, 256, 0, s>>>(w.accp, n);
 }
 
-bool large_set_tile(int n, int d, int precision, int rows, int cols) {
-  for (int t = 0; t < 4; ++t) {
-    if (kTiles[t][0] == rows && kTiles[t][1] == cols) {
+bool large_set_tile(int n, int d, int precision, int rows, int cols, int threads) {
+  for (int t = 0; t < kNumTiles; ++t) {
+    if (kTiles[t][0] == rows && kTiles[t][1] == cols && kTiles[t][2] == threads) {
       int dev = 0;
       (void)hipGetDevice(&dev);
       std::lock_guard<std::mutex> lk(g_tile_mu);
@@ -678,16 +688,17 @@ bool large_set_tile(int n, int d, int precision, int rows, int cols) {
   return false;
 }
 
-int large_tile_choice(int n, int d, int precision, int* cols) {
+int large_tile_choice(int n, int d, int precision, int* cols, int* threads) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   std::lock_guard<std::mutex> lk(g_tile_mu);
   auto it = g_tiles.find(TileKey{dev, n, d, precision});
   if (it == g_tiles.end()) {
-    if (cols) *cols = 0;
+    *cols = *threads = 0;
     return 0;
   }
-  if (cols) *cols = kTiles[it->second][1];
+  *cols = kTiles[it->second][1];
+  *threads = kTiles[it->second][2];
   return kTiles[it->second][0];
 }
 

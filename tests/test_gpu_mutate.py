@@ -128,7 +128,7 @@ def test_increment_is_odd_bitwise(precision, L):
     assert np.any(up != 0)
 
 
-TILES = [(32, 64), (64, 64), (128, 64), (128, 128)]
+TILES = [(32, 64, 256), (64, 64, 256), (128, 64, 256), (128, 128, 256), (128, 128, 512)]
 
 
 @pytest.mark.parametrize("tile", TILES)
