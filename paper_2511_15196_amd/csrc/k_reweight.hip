@@ -138,14 +138,18 @@ __device__ __forceinline__ Grid make_grid(unsigned long long Q, uint32_t U, int 
 // float64 estimate of the quotient (within 1e-11 of it, as the quotient is
 // at most n) fixed by one exact comparison each way.  C n < 2^63 because
 // C <= Q <= n 2^k and n^2 2^k <= 2^62.
+// Branch-free (selects only), so that independent calls overlap.
 __device__ __forceinline__ int count_below(unsigned long long C, const Grid& g) {
   const unsigned long long cn = C * (unsigned long long)g.n;
-  if (cn <= g.off) return 0;
-  const unsigned long long num = cn - g.off;
+  const bool pos = cn > g.off;
+  const unsigned long long num = pos ? cn - g.off : 0ull;
   const double est = ceil((double)num * g.invQ);
   unsigned long long c = est < (double)g.n + 2.0 ? (unsigned long long)est : g.n + 2ull;
-  if (c * g.Q < num) ++c;                       // estimate one too small
-  else if (c > 0 && c * g.Q - g.Q >= num) --c;  // estimate one too large
+  const unsigned long long cq = c * g.Q;
+  const bool small = cq < num;                        // estimate one too small
+  const bool large = !small && c > 0 && cq - g.Q >= num;   // estimate one too large
+  c = small ? c + 1 : (large ? c - 1 : c);
+  c = pos ? c : 0ull;
   return c < (unsigned long long)g.n ? (int)c : g.n;
 }
 
@@ -170,14 +174,17 @@ __device__ void resample_seg(const double (&w)[SEG], int cnt, int i0, int n, dou
   if (cnt > 0 && i0 + cnt == n) qsh = ex + loc;   // Q = C_{n-1}
   __syncthreads();
   const Grid g = make_grid(qsh, U, n);
+  // every range end first (independent), then the writes; past cnt the
+  // running sums stop growing, so those ranges are empty
+  int hi[SEG];
+#pragma unroll
+  for (int k = 0; k < SEG; ++k) hi[k] = count_below(ex + c[k], g);
   int lo = count_below(ex, g);
 #pragma unroll
-  for (int k = 0; k < SEG; ++k)
-    if (k < cnt) {
-      const int hi = count_below(ex + c[k], g);
-      for (int p = lo; p < hi; ++p) anc[p] = i0 + k;
-      lo = hi;
-    }
+  for (int k = 0; k < SEG; ++k) {
+    for (int p = lo; p < hi[k]; ++p) anc[p] = i0 + k;
+    lo = hi[k];
+  }
 }
 
 // Same on global memory for n > kRegN (weights w, scratch cdf and marks).
