@@ -395,7 +395,7 @@ struct FactorArgs {
   int32_t cov_only;        // stop after writing sigma_out
   int32_t* bstatus;        // blocked factor (d > 64): kJitterAttempts + 1 ints of status
   double* Aspec;           // blocked factor: matrices of attempts 1 .. attempts-1, then
-  double* Winv;            //   attempts inverses of 64 x 64 diagonal blocks
+  double* Winv;            //   attempts 64 x 64 factored diagonal blocks (staging)
   int32_t attempts;        // jitter attempts run side by side (blocked_attempts(d))
 };
 // Jitter attempts of the factorisation (tau0, then five times x100).

@@ -559,11 +559,10 @@ __global__ __launch_bounds__(kCF) void cov_factor_kernel(FactorArgs a) {
 // ------------------------------------------------------ blocked factor
 //
 // For d > 64: right-looking Cholesky of Sigma + tau_j I in 64-column panels,
-// one kernel per stage so that every stage uses as many workgroups as it has
-// independent work: the 64 x 64 diagonal block on one workgroup (chol_lds,
-// which also forms the block's inverse), the panel below it as the product
-// A21 L11^-T on FP64 MFMA, and the rank-64 update of the trailing lower tiles
-// on FP64 MFMA.  The jitter attempts tau_j = tau0 100^j (j < attempts) run
+// two kernels per stage: the panel kernel factors the 64 x 64 diagonal block
+// (chol_lds) and its inverse in every workgroup and forms the panel below it
+// as the product A21 L11^-T on FP64 MFMA; the rank-64 update of the trailing
+// lower tiles runs on FP64 MFMA.  The jitter attempts tau_j = tau0 100^j (j < attempts) run
 // side by side in gridDim.y, each on its own copy of the matrix: the
 // sequence of attempts is decided by data the host never sees, and running
 // them together costs one factorisation's latency instead of up to six.  A
@@ -572,7 +571,6 @@ __global__ __launch_bounds__(kCF) void cov_factor_kernel(FactorArgs a) {
 // sequential rule would.  If every attempt fails and fewer than six ran, the
 // single-workgroup factor_kernel continues the escalation.
 
-constexpr int kBT = 256;   // threads of the panel and update stages
 
 __device__ inline double* attempt_matrix(double* A, double* Aspec, int j, int d) {
   return j == 0 ? A : Aspec + (size_t)(j - 1) * d * d;
@@ -613,20 +611,10 @@ __global__ __launch_bounds__(256) void bf_copy_kernel(const double* __restrict__
   if (j <= i) Aj[e] = src[e] + (i == j ? attempt_tau(*tau, blockIdx.y) : 0.0);
 }
 
-// Diagonal block kb: factor in LDS (padded with the identity past d), and,
-// when rows remain below it, the inverse W = L11^-1 for the panel stage.
-__global__ __launch_bounds__(kCF) void bf_diag_kernel(double* __restrict__ A,
-                                                      double* __restrict__ Aspec,
-                                                      double* __restrict__ Winv, int d, int kb,
-                                                      int32_t* __restrict__ status,
-                                                      const int32_t* __restrict__ done) {
-  const int at = blockIdx.y;
-  if ((done && *done) || status[at]) return;
-  double* Aj = attempt_matrix(A, Aspec, at, d);
-  __shared__ double M[64][65];
-  __shared__ double col[64];
-  __shared__ double rs[64];
-  __shared__ int flag;
+// Loads the diagonal block kb of Aj into M (padded with the identity past d)
+// and factors it in LDS.  Returns false if a pivot fails (uniform).
+__device__ bool diag_factor(const double* Aj, int d, int kb, double (*M)[65], double* col,
+                            double* rs, int* flag) {
   const int nb = min(64, d - kb);
   for (int e = threadIdx.x; e < 64 * 64; e += kCF) {
     const int r = e >> 6, c = e & 63;
@@ -635,21 +623,14 @@ __global__ __launch_bounds__(kCF) void bf_diag_kernel(double* __restrict__ A,
     M[r][c] = v;
   }
   __syncthreads();
-  if (!chol_lds<64>(M, col, rs, &flag)) {
-    if (threadIdx.x == 0) status[at] = 1;
-    return;
-  }
-  for (int e = threadIdx.x; e < 64 * 64; e += kCF) {
-    const int r = e >> 6, c = e & 63;
-    if (r < nb && c <= r) Aj[(size_t)(kb + r) * d + kb + c] = M[r][c];
-  }
-  if (kb + 64 >= d) return;
-  // W = L^-1 by 16 x 16 blocks: the diagonal blocks W_bb = L_bb^-1 by
-  // forward substitution (lane 16 b + c owns column c of block b), then
-  // W_ij = -W_ii sum_{j <= k < i} L_ik W_kj for i > j, one block distance
-  // i - j at a time (every block it needs is then known).
-  __shared__ double Wl[64][65];
-  __shared__ double Tt[3][16][17];
+  return chol_lds<64>(M, col, rs, flag);
+}
+
+// W = L^-1 of the factored block in M, by 16 x 16 blocks: the diagonal
+// blocks W_bb = L_bb^-1 by forward substitution (lane 16 b + c owns column c
+// of block b), then W_ij = -W_ii sum_{j <= k < i} L_ik W_kj for i > j, one
+// block distance i - j at a time (every block it needs is then known).
+__device__ void diag_inverse(const double (*M)[65], double (*Wl)[65], double (*Tt)[16][17]) {
   const int tid = threadIdx.x;
   for (int e = tid; e < 64 * 64; e += kCF) Wl[e >> 6][e & 63] = 0.0;
   __syncthreads();
@@ -684,32 +665,73 @@ __global__ __launch_bounds__(kCF) void bf_diag_kernel(double* __restrict__ A,
     }
     __syncthreads();
   }
-  double* W = Winv + (size_t)at * 4096;
-  for (int e = tid; e < 64 * 64; e += kCF) W[e] = Wl[e >> 6][e & 63];
 }
 
-// Panel below block kb: X = A21 L11^-T = A21 W^T on FP64 MFMA, 64 rows per
-// workgroup; wave v computes rows 16v..16v+15 as four 16 x 16 tiles.
-__global__ __launch_bounds__(kBT) void bf_trsm_kernel(double* __restrict__ A,
-                                                      double* __restrict__ Aspec,
-                                                      const double* __restrict__ Winv, int d,
-                                                      int kb, const int32_t* __restrict__ status,
+// Last diagonal block (no rows below it): factor in LDS and write back.
+__global__ __launch_bounds__(kCF) void bf_diag_kernel(double* __restrict__ A,
+                                                      double* __restrict__ Aspec, int d, int kb,
+                                                      int32_t* __restrict__ status,
                                                       const int32_t* __restrict__ done) {
   const int at = blockIdx.y;
   if ((done && *done) || status[at]) return;
   double* Aj = attempt_matrix(A, Aspec, at, d);
-  const double* W = Winv + (size_t)at * 4096;
-  __shared__ double Xs[64][65];
-  __shared__ double Ws[64][65];
-  const int r0 = kb + 64 + blockIdx.x * 64;
-  for (int e = threadIdx.x; e < 64 * 64; e += kBT) {
+  __shared__ double M[64][65];
+  __shared__ double col[64];
+  __shared__ double rs[64];
+  __shared__ int flag;
+  if (!diag_factor(Aj, d, kb, M, col, rs, &flag)) {
+    if (threadIdx.x == 0) status[at] = 1;
+    return;
+  }
+  const int nb = min(64, d - kb);
+  for (int e = threadIdx.x; e < 64 * 64; e += kCF) {
+    const int r = e >> 6, c = e & 63;
+    if (r < nb && c <= r) Aj[(size_t)(kb + r) * d + kb + c] = M[r][c];
+  }
+}
+
+// Stage kb with rows below it, one kernel: every workgroup factors the
+// diagonal block and forms its inverse W = L11^-1 in LDS (the same
+// arithmetic in each, so all agree on failure), then solves its 128 panel
+// rows X = A21 L11^-T = A21 W^T on FP64 MFMA (wave v: rows 16v..16v+15 as
+// four 16 x 16 tiles).  The factored block goes to Dfac (workgroup 0): the
+// block itself is still being read by the other workgroups, so the trailing
+// update kernel that follows copies it into place.
+constexpr int kPR = 128;   // panel rows per workgroup
+
+__global__ __launch_bounds__(kCF) void bf_panel_kernel(double* __restrict__ A,
+                                                       double* __restrict__ Aspec,
+                                                       double* __restrict__ Dfac, int d, int kb,
+                                                       int32_t* __restrict__ status,
+                                                       const int32_t* __restrict__ done) {
+  const int at = blockIdx.y;
+  if ((done && *done) || status[at]) return;
+  double* Aj = attempt_matrix(A, Aspec, at, d);
+  __shared__ double M[64][65];
+  __shared__ double Wl[64][65];
+  __shared__ double Tt[3][16][17];
+  __shared__ double Xs[kPR][65];
+  __shared__ double col[64];
+  __shared__ double rs[64];
+  __shared__ int flag;
+  const int tid = threadIdx.x;
+  const int r0 = kb + 64 + blockIdx.x * kPR;
+  // panel rows first (independent of the factor), then the diagonal block
+  for (int e = tid; e < kPR * 64; e += kCF) {
     const int r = e >> 6, c = e & 63;
     const double v = Aj[(size_t)min(r0 + r, d - 1) * d + kb + c];
     Xs[r][c] = r0 + r < d ? v : 0.0;
-    Ws[r][c] = W[e];
   }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (!diag_factor(Aj, d, kb, M, col, rs, &flag)) {
+    if (tid == 0 && blockIdx.x == 0) status[at] = 1;
+    return;
+  }
+  if (blockIdx.x == 0) {
+    double* D = Dfac + (size_t)at * 4096;
+    for (int e = tid; e < 64 * 64; e += kCF) D[e] = M[e >> 6][e & 63];
+  }
+  diag_inverse(M, Wl, Tt);
+  const int lane = tid & 63, wv = tid >> 6;
   const int pl = lane & 15, gl = lane >> 4;
   f64x4 acc[4];
 #pragma unroll
@@ -719,7 +741,7 @@ __global__ __launch_bounds__(kBT) void bf_trsm_kernel(double* __restrict__ A,
     const double av = Xs[16 * wv + pl][4 * kk + gl];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const double bv = Ws[16 * b + pl][4 * kk + gl];   // W^T[k][col] = W[col][k]
+      const double bv = Wl[16 * b + pl][4 * kk + gl];   // W^T[k][col] = W[col][k]
       acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[b], 0, 0, 0);
     }
   }
@@ -736,12 +758,22 @@ __global__ __launch_bounds__(kBT) void bf_trsm_kernel(double* __restrict__ A,
 // below block kb; X is the solved panel.  Wave w computes a 32 x 32 quarter
 // as 2 x 2 FP64 MFMA tiles (K = 4 per instruction).
 __global__ __launch_bounds__(256) void bf_syrk_kernel(double* __restrict__ A,
-                                                      double* __restrict__ Aspec, int d, int kb,
-                                                      const int32_t* __restrict__ status,
+                                                      double* __restrict__ Aspec,
+                                                      const double* __restrict__ Dfac, int d,
+                                                      int kb, const int32_t* __restrict__ status,
                                                       const int32_t* __restrict__ done) {
   const int at = blockIdx.y;
   if ((done && *done) || status[at]) return;
   double* Aj = attempt_matrix(A, Aspec, at, d);
+  if (blockIdx.x == 0) {
+    // the stage's factored diagonal block into place (lower part; rows below
+    // it exist, so the block is full)
+    const double* D = Dfac + (size_t)at * 4096;
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+      const int r = e >> 6, c = e & 63;
+      if (c <= r) Aj[(size_t)(kb + r) * d + kb + c] = D[e];
+    }
+  }
   __shared__ double Xi[64][65];
   __shared__ double Xj[64][65];
   int I = 0, J = blockIdx.x;
@@ -904,14 +936,15 @@ void launch_factor(const FactorArgs& a, hipStream_t s) {
     bf_init_kernel<<<1, 1024, 0, s>>>(src, d, a.tau_out, a.bstatus, P, a.done);
     bf_copy_kernel<<<dim3(nel, P), 256, 0, s>>>(src, a.A, a.Aspec, d, a.tau_out, a.done);
     for (int kb = 0; kb < d; kb += 64) {
-      bf_diag_kernel<<<dim3(1, P), kCF, 0, s>>>(a.A, a.Aspec, a.Winv, d, kb, a.bstatus, a.done);
       const int below = d - kb - 64;
       if (below > 0) {
         const int nt = (below + 63) / 64;
-        bf_trsm_kernel<<<dim3(nt, P), kBT, 0, s>>>(a.A, a.Aspec, a.Winv, d, kb, a.bstatus,
-                                                   a.done);
-        bf_syrk_kernel<<<dim3(nt * (nt + 1) / 2, P), 256, 0, s>>>(a.A, a.Aspec, d, kb,
+        bf_panel_kernel<<<dim3((below + kPR - 1) / kPR, P), kCF, 0, s>>>(
+            a.A, a.Aspec, a.Winv, d, kb, a.bstatus, a.done);
+        bf_syrk_kernel<<<dim3(nt * (nt + 1) / 2, P), 256, 0, s>>>(a.A, a.Aspec, a.Winv, d, kb,
                                                                   a.bstatus, a.done);
+      } else {
+        bf_diag_kernel<<<dim3(1, P), kCF, 0, s>>>(a.A, a.Aspec, d, kb, a.bstatus, a.done);
       }
     }
     bf_emit_kernel<<<nel, 256, 0, s>>>(a.A, a.Aspec, d, a.Bt, a.ldb, a.eps_ptr, a.tau_out,
