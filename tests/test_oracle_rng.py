@@ -7,21 +7,8 @@ from scipy import stats
 from oracle import rng
 
 
-# Known-answer vectors distributed with the Philox4x32-10 publication
-# (Salmon et al., SC'11): (counter, key) -> output, all 32-bit words.
-KAT = [
-    ((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
-    ((0xFFFFFFFF,) * 4, (0xFFFFFFFF,) * 2,
-     (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
-    ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
-     (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1)),
-]
-
-
-@pytest.mark.parametrize("ctr,key,out", KAT)
-def test_philox_known_answers(ctr, key, out):
-    got = rng.philox4x32_10(*ctr, *key)
-    assert tuple(int(x) for x in got) == out
+# The published known-answer vectors are pinned in test_oracle_golden.py
+# (tests/golden/philox4x32_10_kat.txt).
 
 
 def test_philox_broadcasts_like_scalar_calls():
