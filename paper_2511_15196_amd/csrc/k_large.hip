@@ -4,7 +4,10 @@
 //
 //   1. normals:  z[p][k] from the PROPOSE stream (App. A random-walk
 //      kernel), float32 or rounded to bfloat16 / float16, materialised in
-//      HBM (z is shared by every column tile of the product);
+//      HBM (z is shared by every column tile of the product); drawn by a
+//      pass of their own for the first step of a sweep and by the accept
+//      pass of the step before for the others (its ALUs are idle while its
+//      row loads are in flight);
 //   2. proposal: phi'[p][c] = phi[p][c] + sum_{k <= c} z[p][k] Bt[k][c] on the
 //      matrix cores, 64 x 64 output tiles staged through LDS, only the
 //      K range on or above the diagonal of the triangular factor; the
@@ -350,6 +353,12 @@ struct AcceptArgs {
   float* absM;
   int32_t* accp;             // per-slot acceptance counts
   uint8_t* acc_flags;        // optional, per slot (this step)
+  // optional: the normals of the next step for this slot, drawn while the
+  // row loads are in flight (the same values the normals pass would write)
+  float* znext;              // z of the next step, layout of z_kernel (NULL: none)
+  unsigned short* zsgn;      // 16-bit forms: sign bit of each row's first normal
+  int dz, zprec;
+  float zsign;
 };
 
 template <bool CONSTRAINED, int PER>   // PER >= d / kAT sites per thread
@@ -372,6 +381,33 @@ __global__ __launch_bounds__(kAT) void accept_kernel(AcceptArgs a) {
       const int x = min(tid + i * kAT, d - 1);
       vo[i] = cp[x];
       vn[i] = pp[x];
+    }
+    if (a.znext && !(a.done && *a.done)) {
+      const uint32_t c3p =
+          counter3((uint32_t)(a.level_ptr ? *a.level_ptr : a.level), PHI4_PROPOSE);
+      const int nq = a.dz / 4;
+      for (int q = tid; q < nq; q += kAT) {
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (4 * q < d) {
+          v = normals4((uint32_t)q, (uint32_t)orw, a.step + 1, c3p, a.seed, a.run);
+          v.x *= a.zsign;
+          v.y *= a.zsign;
+          v.z *= a.zsign;
+          v.w *= a.zsign;
+        }
+        if (a.zprec == PHI4_FP32) {
+          *reinterpret_cast<float4*>(a.znext + (size_t)p * a.dz + 4 * q) = v;
+        } else {
+          ushort4 h;
+          h.x = to16(v.x, a.zprec);
+          h.y = to16(v.y, a.zprec);
+          h.z = to16(v.z, a.zprec);
+          h.w = to16(v.w, a.zprec);
+          *reinterpret_cast<ushort4*>(reinterpret_cast<unsigned short*>(a.znext) +
+                                      (size_t)p * a.dz + 4 * q) = h;
+          if (q == 0) a.zsgn[p] = h.x & 0x8000u;
+        }
+      }
     }
 #pragma unroll
     for (int i = 0; i < PER; ++i)
@@ -521,11 +557,15 @@ void enqueue_step(const MutateArgs& a, const LargeScratch& w, int tile, int s, b
                   hipStream_t st) {
   const int n = a.n, d = a.d, dz = large_dz(d);
   const uint32_t step = (uint32_t)(a.step0 + s);
-  const long long nz = (long long)n * (dz / 4);
-  z_kernel<PREC><<<(unsigned)((nz + 255) / 256), 256, 0, st>>>(w.z, n, d, dz, a.rows, step,
-                                                               a.level, a.level_ptr, a.seed,
-                                                               a.run, a.zsign, w.zsgn,
-                                                               a.done_ptr);
+  // the normals of the first step; each later step's are drawn by the
+  // accept pass of the step before
+  if (first) {
+    const long long nz = (long long)n * (dz / 4);
+    z_kernel<PREC><<<(unsigned)((nz + 255) / 256), 256, 0, st>>>(w.z, n, d, dz, a.rows, step,
+                                                                 a.level, a.level_ptr, a.seed,
+                                                                 a.run, a.zsign, w.zsgn,
+                                                                 a.done_ptr);
+  }
   // current fields: the step-0 source (through its row maps) or the output
   const float* cur = first ? a.src : a.dst;
   const int32_t* crows = first ? (a.src_rows ? a.src_rows : a.rows) : a.rows;
@@ -558,6 +598,13 @@ void enqueue_step(const MutateArgs& a, const LargeScratch& w, int tile, int s, b
   aa.absM = a.absM;
   aa.accp = w.accp;
   aa.acc_flags = (s == a.n_steps - 1) ? a.acc_flags : nullptr;
+  if (s + 1 < a.n_steps) {
+    aa.znext = w.z;
+    aa.zsgn = w.zsgn;
+    aa.dz = dz;
+    aa.zprec = PREC;
+    aa.zsign = a.zsign;
+  }
   const size_t lds = 2 * (size_t)d * sizeof(float);
   const int per = (d + kAT - 1) / kAT;
   if (a.kind == 1)
