@@ -278,8 +278,23 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const void* __restrict__ zin,
       if (u < nkt) gload(ra[u % S], rb[u % S], c0, u);
     __syncthreads();
     // tile kt is multiplied from LDS buffer kt & 1 while tiles kt+1 .. kt+S
-    // are in flight; a load has S tiles of work to land
-    for (int kt0 = 0; kt0 < nkt; kt0 += S) {
+    // are in flight; a load has S tiles of work to land.  The steady-state
+    // loop issues every load unconditionally, so that the wait before each
+    // store counts only the loads it needs (a conditional load makes the
+    // compiler wait for all of them); the tail handles the last tiles.
+    int kt0 = 0;
+    for (; kt0 + 2 * S < nkt; kt0 += S) {
+#pragma unroll
+      for (int u = 0; u < S; ++u) {
+        const int kt = kt0 + u;
+        compute(u & 1);
+        sstore(ra[(u + 1) % S], rb[(u + 1) % S], (u + 1) & 1);
+        __syncthreads();
+        gload(ra[(u + 1) % S], rb[(u + 1) % S], c0, kt + 1 + S);
+        __builtin_amdgcn_sched_barrier(0);   // issue the loads here, not after the next tile
+      }
+    }
+    for (; kt0 < nkt; kt0 += S) {
 #pragma unroll
       for (int u = 0; u < S; ++u) {
         const int kt = kt0 + u;
