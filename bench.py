@@ -42,7 +42,7 @@ VALU_PEAK = 256 * 4 * 16 * 2.4e9
 # valid only for the kernel sources they were taken on.
 TRAFFIC = dict(bytes_per_launch=(516.40 * 1.99980 + 1072.0) * 1024,
                sources={"k_mutate.hip": "9d73ba65343919455708a3e7da700cc69f132734f4ba260e38d111557c397d9c",
-                        "common.hpp": "358094e7cd9e45b5e8f59514c842bf83ba930c10b9e38d461d9bf97c55e9cad7"})
+                        "common.hpp": "4097ce027518c90000269a1063c71e114baf0749c9547a9753dffa4777d92be5"})
 
 
 def traffic_per_launch():
