@@ -56,11 +56,24 @@ enum { PHI4_FP32 = 0, PHI4_BF16 = 1, PHI4_FP16 = 2 };
 /* Philox stream purposes (low byte of counter word 3). */
 enum { PHI4_INIT = 1, PHI4_PROPOSE = 2, PHI4_ACCEPT = 3, PHI4_RESAMPLE = 4, PHI4_NS_PICK = 5 };
 
-/* Largest lattice the fused mutation kernel handles: d = L*L <= 256. */
+/* Largest lattice, d = L*L sites: the register-resident fused sweep covers
+ * d <= 256, the three-pass sweep the rest. */
 #define PHI4_MAX_SITES 4096
 
+/* Inner (rejuvenation) kernels of SMC.
+ * PHI4_KERNEL_RW: random-walk Metropolis, phi' = phi + eps L z (Sec. 2 (i);
+ *   App. A), eps adapted per level toward acc_target.
+ * PHI4_KERNEL_IRMH: independent Metropolis-Hastings (Sec. 2 (ii); App. A),
+ *   phi' = mu + L z with mu and L L^T the mean and the jittered covariance
+ *   of the resampled particles, log alpha = -dU0 - beta dS + (|z|^2 - r) / 2
+ *   with r = |L^{-1}(phi - mu)|^2 of the current particle.  float32 only,
+ *   d <= PHI4_IRMH_MAX_SITES; eps0 and acc_target are unused (the eps that
+ *   phi4_observables reports is then meaningless). */
+enum { PHI4_KERNEL_RW = 0, PHI4_KERNEL_IRMH = 1 };
+#define PHI4_IRMH_MAX_SITES 1024
+
 /* One adaptive tempered SMC run (Sec. 2 "Particle-based Monte Carlo
- * methods" (i); App. A).  Target p_beta ~ exp(-[U0 + beta S]) with
+ * methods" (i), (ii); App. A).  Target p_beta ~ exp(-[U0 + beta S]) with
  * U0 = |phi|^2 / 2 and S the action of Sec. 2 Eq. (1); log Z estimates
  * log E_{phi ~ N(0, I)}[exp(-S(phi))]. */
 typedef struct phi4_smc_config {
@@ -75,6 +88,7 @@ typedef struct phi4_smc_config {
   uint32_t seed;        /* Philox key word 0 */
   uint32_t run;         /* Philox key word 1 */
   int32_t precision;    /* PHI4_FP32 / PHI4_BF16 / PHI4_FP16 */
+  int32_t kernel;       /* inner kernel: PHI4_KERNEL_RW (0) or PHI4_KERNEL_IRMH (1) */
 } phi4_smc_config;
 
 /* One nested-sampling run (Sec. 2 (iv); App. A) with a likelihood-
@@ -297,6 +311,20 @@ int phi4_cholesky(const double* sigma, int32_t d, double* L, double* tau_host,
 
 /* Workspace bytes the step-level entry points need for N particles of d sites. */
 size_t phi4_step_workspace_bytes(int32_t N, int32_t d);
+
+/* Whitened residuals of the independence sampler's current particles
+ * (Sec. 2 (ii); App. A: the proposal density N(mu, L L^T) at phi is
+ * proportional to exp(-r / 2)): mu = mean of the rows phi[rows[i]] (rows
+ * NULL: rows 0..N-1) and r[i] = |L^{-1}(phi[rows[i]] - mu)|^2 for the lower
+ * factor L (float64, d*d row-major, nonzero diagonal; the upper part is not
+ * read), all arithmetic in float64.  r (N floats) and mu (optional, d floats)
+ * receive the results rounded to float32.  Needs 1 <= N, 1 <= d <=
+ * PHI4_IRMH_MAX_SITES and workspace >= phi4_whiten_workspace_bytes(N, d)
+ * (256-byte aligned); returns PHI4_EINVAL otherwise.  Asynchronous on
+ * stream. */
+size_t phi4_whiten_workspace_bytes(int32_t N, int32_t d);
+int phi4_whiten(const float* phi, const int32_t* rows, int32_t N, int32_t d, const double* L,
+                float* r, float* mu, void* workspace, size_t workspace_bytes, void* stream);
 
 /* n_steps fused Metropolis steps of the rows of src selected by rows
  * (rows NULL: rows 0..n-1), written to the same rows of dst (dst may equal

@@ -15,8 +15,8 @@ from . import _abi
 from ._abi import (  # noqa: F401
     PHI4_OK, PHI4_DONE, PHI4_EINVAL, PHI4_EHIP, PHI4_ECHOL, PHI4_ENONFINITE,
     PHI4_FP32, PHI4_BF16, PHI4_FP16, PHI4_INIT, PHI4_PROPOSE, PHI4_ACCEPT,
-    PHI4_RESAMPLE, PHI4_NS_PICK, PHI4_MAX_SITES, Phi4Error, SmcConfig, NsConfig,
-    lib, library_path,
+    PHI4_RESAMPLE, PHI4_NS_PICK, PHI4_MAX_SITES, PHI4_KERNEL_RW, PHI4_KERNEL_IRMH,
+    PHI4_IRMH_MAX_SITES, KERNELS, Phi4Error, SmcConfig, NsConfig, lib, library_path,
 )
 
 PRECISIONS = {"fp32": PHI4_FP32, "bf16": PHI4_BF16, "fp16": PHI4_FP16}
@@ -219,6 +219,17 @@ def phi4_covariance(phi, N, d, sigma, workspace, rows=None, stream=None):
                                  _stream(stream)), "phi4_covariance")
 
 
+def phi4_whiten_workspace_bytes(n, d):
+    return lib().phi4_whiten_workspace_bytes(ctypes.c_int32(n), ctypes.c_int32(d))
+
+
+def phi4_whiten(phi, N, d, L, r, workspace, rows=None, mu=None, stream=None):
+    _require_cuda(phi, L, r, workspace, rows, mu)
+    _check(lib().phi4_whiten(_ptr(phi), _ptr(rows), ctypes.c_int32(N), ctypes.c_int32(d), _ptr(L),
+                             _ptr(r), _ptr(mu), _ptr(workspace), ctypes.c_size_t(workspace.numel()),
+                             _stream(stream)), "phi4_whiten")
+
+
 def phi4_cholesky(sigma, d, L, workspace, stream=None):
     _require_cuda(sigma, L, workspace)
     tau = ctypes.c_double()
@@ -254,11 +265,11 @@ class SMC:
     """One adaptive tempered SMC run with torch-owned device buffers."""
 
     def __init__(self, L, N, m2, lam, ess_frac=0.5, n_steps=10, acc_target=0.3, eps0=0.0,
-                 seed=0, run=0, precision="fp32", sweep="auto", device="cuda"):
+                 seed=0, run=0, precision="fp32", sweep="auto", device="cuda", kernel="rw"):
         import torch
         self.cfg = SmcConfig(L=L, N=N, m2=m2, lambda_=lam, ess_frac=ess_frac, n_steps=n_steps,
                              acc_target=acc_target, eps0=eps0, seed=seed, run=run,
-                             precision=PRECISIONS[precision])
+                             precision=PRECISIONS[precision], kernel=KERNELS[kernel])
         nbytes = smc_workspace_bytes(self.cfg)
         if nbytes == 0:
             raise Phi4Error(PHI4_EINVAL, "invalid SMC configuration")

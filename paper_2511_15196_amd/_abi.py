@@ -8,6 +8,9 @@ PHI4_EINVAL, PHI4_EHIP, PHI4_ECHOL, PHI4_ENONFINITE = -1, -2, -3, -4
 PHI4_FP32, PHI4_BF16, PHI4_FP16 = 0, 1, 2
 PHI4_INIT, PHI4_PROPOSE, PHI4_ACCEPT, PHI4_RESAMPLE, PHI4_NS_PICK = 1, 2, 3, 4, 5
 PHI4_MAX_SITES = 4096
+PHI4_KERNEL_RW, PHI4_KERNEL_IRMH = 0, 1
+PHI4_IRMH_MAX_SITES = 1024
+KERNELS = {"rw": PHI4_KERNEL_RW, "irmh": PHI4_KERNEL_IRMH}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libphi4pmc.so")
@@ -32,6 +35,7 @@ class SmcConfig(ctypes.Structure):
         ("seed", ctypes.c_uint32),
         ("run", ctypes.c_uint32),
         ("precision", ctypes.c_int32),
+        ("kernel", ctypes.c_int32),
     ]
 
 
@@ -89,6 +93,8 @@ SIGNATURES = {
     "phi4_resample_systematic": (ctypes.c_int, [_V, _I32, _U32, _V, _V, _SZ, _V]),
     "phi4_reweight": (ctypes.c_int, [_V, _I32, _D, _D, _V, _PD, _V, _SZ, _V]),
     "phi4_covariance": (ctypes.c_int, [_V, _V, _I32, _I32, _V, _V, _SZ, _V]),
+    "phi4_whiten_workspace_bytes": (ctypes.c_size_t, [_I32, _I32]),
+    "phi4_whiten": (ctypes.c_int, [_V, _V, _I32, _I32, _V, _V, _V, _V, _SZ, _V]),
     "phi4_cholesky": (ctypes.c_int, [_V, _I32, _V, _PD, _V, _SZ, _V]),
     "phi4_step_workspace_bytes": (_SZ, [_I32, _I32]),
     "phi4_mutate": (ctypes.c_int, [_V, _V, _V, _I32, _I32, _D, _D, _V, _I32, _D, _D, _D, _U32,

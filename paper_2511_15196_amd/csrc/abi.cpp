@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "irmh.hpp"
 
 using namespace phi4;
 
@@ -84,6 +85,7 @@ struct SmcBufs {
   LargeScratch large;
   int32_t* bstatus;
   double* bscr;
+  IrmhScratch irmh;   // independence sampler only
 };
 
 // Blocked-factor fields of FactorArgs from its carved scratch.
@@ -118,6 +120,11 @@ size_t smc_carve(const phi4_smc_config& c, void* ws, SmcBufs* b) {
   t.large = take_large(cv, n, d);
   t.bstatus = cv.take<int32_t>(kJitterAttempts + 1);
   t.bscr = cv.take<double>(blocked_scratch_doubles(d));
+  t.irmh = IrmhScratch{};
+  if (c.kernel == PHI4_KERNEL_IRMH) {
+    char* base = cv.take<char>(irmh_scratch_bytes(n, d));
+    if (cv.base) t.irmh = irmh_scratch(base, n, d);
+  }
   if (b) *b = t;
   return cv.bytes();
 }
@@ -131,6 +138,12 @@ bool smc_valid(const phi4_smc_config* c, std::string* why) {
   if (c->n_steps < 0) return *why = "n_steps must be >= 0", false;
   if (!std::isfinite(c->m2) || !std::isfinite(c->lambda)) return *why = "couplings must be finite", false;
   if (!mutate_supported((int)d, c->precision)) return *why = "unsupported precision", false;
+  if (c->kernel != PHI4_KERNEL_RW && c->kernel != PHI4_KERNEL_IRMH)
+    return *why = "unknown inner kernel", false;
+  if (c->kernel == PHI4_KERNEL_IRMH && c->precision != PHI4_FP32)
+    return *why = "the independence sampler runs in float32 only", false;
+  if (c->kernel == PHI4_KERNEL_IRMH && d > PHI4_IRMH_MAX_SITES)
+    return *why = "the independence sampler needs L*L <= 1024", false;
   return true;
 }
 
@@ -265,7 +278,8 @@ int enqueue_reweight(Handle* h, SmcState* mirror = nullptr) {
   fa.A = b.A;
   fa.Bt = b.Bt;
   fa.ldb = h->d;
-  fa.eps_ptr = &b.st->eps;
+  // the independence sampler proposes with L itself
+  fa.eps_ptr = h->smc.kernel == PHI4_KERNEL_IRMH ? b.irmh.one : &b.st->eps;
   fa.tau_out = &b.st->tau;
   fa.err_out = &b.st->err;
   fa.done = &b.st->done;
@@ -308,7 +322,10 @@ int enqueue_mutate(Handle* h) {
   int rc;
   {
     TimedLaunch tl(h);
-    rc = launch_mutate(m, h->precision, h->stream);
+    if (h->smc.kernel == PHI4_KERNEL_IRMH)
+      rc = launch_irmh_sweep(m, b.A, b.irmh, h->stream);
+    else
+      rc = launch_mutate(m, h->precision, h->stream);
   }
   if (rc) return fail(rc, "smc_mutate: unsupported shape");
   h->cur ^= 1;
@@ -509,6 +526,7 @@ int smc_init(const phi4_smc_config* cfg, float* phi, float* S, void* workspace,
   smc_carve(*cfg, workspace, &h->sb);
   launch_cov_init(h->sb.part, h->plan, h->stream);
   launch_large_init(h->sb.large, h->n, h->stream);
+  if (cfg->kernel == PHI4_KERNEL_IRMH) launch_irmh_init(h->sb.irmh, h->stream);
   int rc = alloc_pinned(h, sizeof(SmcState));
   if (rc) {
     delete h;
@@ -1076,6 +1094,28 @@ int phi4_reweight(const float* S, int32_t N, double beta, double ess_frac, doubl
   HIP_TRY(hipStreamSynchronize(s));
   if (!std::isfinite(out_host[0])) return fail(PHI4_ENONFINITE, "phi4_reweight: non-finite actions or stalled solve");
   return PHI4_OK;
+}
+
+size_t phi4_whiten_workspace_bytes(int32_t N, int32_t d) {
+  if (N < 1 || d < 1 || d > PHI4_IRMH_MAX_SITES) return 0;
+  return irmh_scratch_bytes(N, d);
+}
+
+int phi4_whiten(const float* phi, const int32_t* rows, int32_t N, int32_t d, const double* L,
+                float* r, float* mu, void* workspace, size_t workspace_bytes, void* stream) {
+  std::string why;
+  if (N < 1 || d < 1 || d > PHI4_IRMH_MAX_SITES || !phi || !L || !r)
+    return fail(PHI4_EINVAL, "phi4_whiten: need N >= 1, 1 <= d <= 1024 and phi, L, r");
+  if (!ws_ok(workspace, workspace_bytes, irmh_scratch_bytes(N, d), &why))
+    return fail(PHI4_EINVAL, "phi4_whiten: " + why);
+  IrmhScratch q = irmh_scratch(workspace, N, d);
+  q.r = r;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  launch_irmh_mean(phi, rows, N, d, q, nullptr, s);
+  launch_irmh_inverse(L, d, q, nullptr, s);
+  launch_irmh_whiten(phi, rows, N, d, q, nullptr, s);
+  if (mu) HIP_TRY(hipMemcpyAsync(mu, q.mu, sizeof(float) * d, hipMemcpyDeviceToDevice, s));
+  return hip_check("phi4_whiten");
 }
 
 int phi4_covariance(const float* phi, const int32_t* rows, int32_t N, int32_t d, double* sigma,

@@ -28,6 +28,7 @@
 #include <type_traits>
 
 #include "common.hpp"
+#include "irmh.hpp"
 
 namespace phi4 {
 
@@ -121,7 +122,9 @@ __global__ __launch_bounds__(256) void lp_kernel(const float* __restrict__ Bt, i
   }
 }
 
-// phi'[p][c] = phi[irow(p)][c] + sum_{k <= c} z[p][k] Lp[c][k].
+// phi'[p][c] = phi[irow(p)][c] + sum_{k <= c} z[p][k] Lp[c][k]; the base rows
+// are ldphi floats apart (0: one row for every particle, the independence
+// sampler's mean).
 //
 // Workgroup tile BM particles x BN columns, 4 waves as 2 x 2 (each
 // BM/2 x BN/2 as 16 x 16 MFMA fragments), K in tiles of 64 through
@@ -146,7 +149,8 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const void* __restrict__ zin,
                                                    const float* __restrict__ phi,
                                                    const int32_t* __restrict__ irows,
                                                    float* __restrict__ prop, int n, int d,
-                                                   int dz, const int32_t* __restrict__ done) {
+                                                   int dz, int ldphi,
+                                                   const int32_t* __restrict__ done) {
   if (done && *done) return;
   constexpr bool F32 = PREC == PHI4_FP32;
   using T = typename std::conditional<F32, float, unsigned short>::type;
@@ -326,7 +330,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const void* __restrict__ zin,
       for (int j = 0; j < FN; ++j) {
         const int cc = min(c0 + wc * WN + 16 * j + pl, d - 1);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) old[i][j][r] = phi[(size_t)irw[i][r] * d + cc];
+        for (int r = 0; r < 4; ++r) old[i][j][r] = phi[(size_t)irw[i][r] * ldphi + cc];
       }
 #pragma unroll
     for (int i = 0; i < FM; ++i)
@@ -374,18 +378,26 @@ struct AcceptArgs {
   unsigned short* zsgn;      // 16-bit forms: sign bit of each row's first normal
   int dz, zprec;
   float zsign;
+  // independence sampler: log alpha gains (|z|^2 - r) / 2 with r the
+  // whitened residual of the slot's current field (replaced by |z|^2 on
+  // acceptance); |z|^2 of the next step's normals is summed while drawing them
+  float* r;
+  const float* zz_in;
+  float* zz_out;
 };
 
-template <bool CONSTRAINED, int PER>   // PER >= d / kAT sites per thread
+template <bool CONSTRAINED, int PER, bool IND = false>   // PER >= d / kAT sites per thread
 __global__ __launch_bounds__(kAT) void accept_kernel(AcceptArgs a) {
+  constexpr int NV = IND ? 7 : 6;   // reduced sums
   extern __shared__ __align__(16) float rowbuf[];   // d pairs (phi, phi')
-  __shared__ float red[kAT / 64][6];
+  __shared__ float red[kAT / 64][NV];
   __shared__ int dec;
   const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int d = a.d, L = a.L;
   const int cr = a.crows ? a.crows[p] : p;
   const int orw = a.orows ? a.orows[p] : p;
   float2* f = reinterpret_cast<float2*>(rowbuf);
+  float zq = 0.f;   // |z|^2 of this thread's share of the next step's normals
   {
     // every load of this thread in flight before the first LDS store
     const float* cp = a.cur + (size_t)cr * d;
@@ -410,6 +422,7 @@ __global__ __launch_bounds__(kAT) void accept_kernel(AcceptArgs a) {
           v.z *= a.zsign;
           v.w *= a.zsign;
         }
+        if constexpr (IND) zq += (v.x * v.x + v.y * v.y) + (v.z * v.z + v.w * v.w);
         if (a.zprec == PHI4_FP32) {
           *reinterpret_cast<float4*>(a.znext + (size_t)p * a.dz + 4 * q) = v;
         } else {
@@ -453,17 +466,24 @@ __global__ __launch_bounds__(kAT) void accept_kernel(AcceptArgs a) {
     col += cstep;
     if (col >= L) col -= L;
   }
-  float v[6] = {so, sn, ds, du, mo, mn};
+  float v[NV];
+  v[0] = so;
+  v[1] = sn;
+  v[2] = ds;
+  v[3] = du;
+  v[4] = mo;
+  v[5] = mn;
+  if constexpr (IND) v[6] = zq;
 #pragma unroll
-  for (int q = 0; q < 6; ++q) v[q] = wave_sum_f(v[q]);
+  for (int q = 0; q < NV; ++q) v[q] = wave_sum_f(v[q]);
   if (lane == 0) {
 #pragma unroll
-    for (int q = 0; q < 6; ++q) red[wv][q] = v[q];
+    for (int q = 0; q < NV; ++q) red[wv][q] = v[q];
   }
   __syncthreads();
   if (tid == 0) {
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
+    for (int q = 0; q < NV; ++q) {
       float t = red[0][q];
       for (int w = 1; w < kAT / 64; ++w) t += red[w][q];
       v[q] = t;
@@ -474,12 +494,19 @@ __global__ __launch_bounds__(kAT) void accept_kernel(AcceptArgs a) {
     int acc;
     if constexpr (!CONSTRAINED) {
       const float beta = a.beta_ptr ? (float)(*a.beta_ptr) : a.beta;
-      acc = lu < -v[3] - beta * v[2];
+      if constexpr (IND)
+        acc = lu < -v[3] - beta * v[2] + 0.5f * (a.zz_in[p] - a.r[p]);
+      else
+        acc = lu < -v[3] - beta * v[2];
     } else {
       const float sstar = a.sstar_ptr ? *a.sstar_ptr : a.s_star;
       acc = (v[1] < sstar) && (lu < -v[3] * a.inv_prior_var);
     }
     if (frozen) acc = 0;
+    if constexpr (IND) {
+      if (acc) a.r[p] = a.zz_in[p];
+      if (a.znext) a.zz_out[p] = v[6];
+    }
     dec = acc;
     a.S[orw] = acc ? v[1] : v[0];
     if (a.absM) a.absM[orw] = fabsf((acc ? v[5] : v[4]) / d);
@@ -525,7 +552,8 @@ constexpr int kTiles[kNumTiles][3] = {
 
 template <int PREC>
 void launch_gemm(int tile, const LargeScratch& w, const float* cur, const int32_t* crows, int n,
-                 int d, const int32_t* done, hipStream_t st) {
+                 int d, const int32_t* done, hipStream_t st, int ldphi = -1) {
+  if (ldphi < 0) ldphi = d;
   const int dz = large_dz(d);
   const int bm = kTiles[tile][0], bn = kTiles[tile][1];
   const int J = (d + bn - 1) / bn;
@@ -533,43 +561,46 @@ void launch_gemm(int tile, const LargeScratch& w, const float* cur, const int32_
   switch (tile) {
     case 0:
       gemm_kernel<PREC, 32, 64, 2><<<grid, 256, 0, st>>>(w.z, w.zsgn, w.lp, cur, crows, w.prop, n, d,
-                                                      dz, done);
+                                                      dz, ldphi, done);
       break;
     case 2:
       gemm_kernel<PREC, 128, 64, 2><<<grid, 256, 0, st>>>(w.z, w.zsgn, w.lp, cur, crows, w.prop, n, d,
-                                                       dz, done);
+                                                       dz, ldphi, done);
       break;
     case 3:
       gemm_kernel<PREC, 128, 128, PREC == PHI4_FP32 ? 2 : 4><<<grid, 256, 0, st>>>(
-          w.z, w.zsgn, w.lp, cur, crows, w.prop, n, d, dz, done);
+          w.z, w.zsgn, w.lp, cur, crows, w.prop, n, d, dz, ldphi, done);
       break;
     case 4:
       gemm_kernel<PREC, 128, 128, 2, 512><<<grid, 512, 0, st>>>(
-          w.z, w.zsgn, w.lp, cur, crows, w.prop, n, d, dz, done);
+          w.z, w.zsgn, w.lp, cur, crows, w.prop, n, d, dz, ldphi, done);
       break;
     default:
       gemm_kernel<PREC, 64, 64, 2><<<grid, 256, 0, st>>>(w.z, w.zsgn, w.lp, cur, crows, w.prop, n, d,
-                                                      dz, done);
+                                                      dz, ldphi, done);
       break;
   }
 }
 
-template <bool CONSTRAINED>
+template <bool CONSTRAINED, bool IND = false>
 void launch_accept(int per, int n, size_t lds, const AcceptArgs& aa, hipStream_t st) {
   static_assert(PHI4_MAX_SITES <= 16 * kAT, "accept stages at most 16 sites per thread");
   if (per <= 2)
-    accept_kernel<CONSTRAINED, 2><<<n, kAT, lds, st>>>(aa);
+    accept_kernel<CONSTRAINED, 2, IND><<<n, kAT, lds, st>>>(aa);
   else if (per <= 4)
-    accept_kernel<CONSTRAINED, 4><<<n, kAT, lds, st>>>(aa);
+    accept_kernel<CONSTRAINED, 4, IND><<<n, kAT, lds, st>>>(aa);
   else if (per <= 8)
-    accept_kernel<CONSTRAINED, 8><<<n, kAT, lds, st>>>(aa);
+    accept_kernel<CONSTRAINED, 8, IND><<<n, kAT, lds, st>>>(aa);
   else
-    accept_kernel<CONSTRAINED, 16><<<n, kAT, lds, st>>>(aa);
+    accept_kernel<CONSTRAINED, 16, IND><<<n, kAT, lds, st>>>(aa);
 }
 
+// One step.  With q (independence sampler, float32): the proposal is
+// mu + z L^T (one base row), |z|^2 of the first step's normals is summed
+// by its own pass and the accept adds the proposal-density ratio.
 template <int PREC>
 void enqueue_step(const MutateArgs& a, const LargeScratch& w, int tile, int s, bool first,
-                  hipStream_t st) {
+                  hipStream_t st, const IrmhScratch* q = nullptr) {
   const int n = a.n, d = a.d, dz = large_dz(d);
   const uint32_t step = (uint32_t)(a.step0 + s);
   // the normals of the first step; each later step's are drawn by the
@@ -580,11 +611,15 @@ void enqueue_step(const MutateArgs& a, const LargeScratch& w, int tile, int s, b
                                                                  a.level, a.level_ptr, a.seed,
                                                                  a.run, a.zsign, w.zsgn,
                                                                  a.done_ptr);
+    if (q) launch_rowsq(w.z, dz, n, d, q->zz, a.done_ptr, st);
   }
   // current fields: the step-0 source (through its row maps) or the output
   const float* cur = first ? a.src : a.dst;
   const int32_t* crows = first ? (a.src_rows ? a.src_rows : a.rows) : a.rows;
-  launch_gemm<PREC>(tile, w, cur, crows, n, d, a.done_ptr, st);
+  if (q)
+    launch_gemm<PREC>(tile, w, q->mu, nullptr, n, d, a.done_ptr, st, 0);
+  else
+    launch_gemm<PREC>(tile, w, cur, crows, n, d, a.done_ptr, st);
   AcceptArgs aa = {};
   aa.cur = cur;
   aa.crows = crows;
@@ -622,7 +657,12 @@ void enqueue_step(const MutateArgs& a, const LargeScratch& w, int tile, int s, b
   }
   const size_t lds = 2 * (size_t)d * sizeof(float);
   const int per = (d + kAT - 1) / kAT;
-  if (a.kind == 1)
+  if (q) {
+    aa.r = q->r;
+    aa.zz_in = q->zz + (size_t)(s & 1) * n;
+    aa.zz_out = q->zz + (size_t)((s + 1) & 1) * n;
+    launch_accept<false, true>(per, n, lds, aa, st);
+  } else if (a.kind == 1)
     launch_accept<true>(per, n, lds, aa, st);
   else
     launch_accept<false>(per, n, lds, aa, st);
@@ -797,6 +837,33 @@ int launch_mutate_large(const MutateArgs& a, const LargeScratch& w, int precisio
     if (e != hipSuccess) return PHI4_EHIP;
   }
   acc_sum_kernel<<<1, 1024, 0, s>>>(w.accp, a.n, a.n_steps, a.acc_count, a.prop_count, a.done_ptr);
+  return PHI4_OK;
+}
+
+// One sweep of the independence sampler (float32 steps): the mean, the
+// inverse factor and the whitened residuals r = |(phi - mu) L^{-T}|^2 of
+// the particles src[src_rows] (float64), then n_steps steps of normals,
+// proposal mu + z L^T and accept.  A sweep of zero steps only moves the rows.
+int launch_irmh_sweep(const MutateArgs& a, const double* A, const IrmhScratch& q,
+                      hipStream_t s) {
+  if (a.n <= 0) return PHI4_OK;
+  if (a.n_steps == 0) return launch_mutate_large(a, a.large, PHI4_FP32, s);
+  const int n = a.n, d = a.d, dz = large_dz(d);
+  const LargeScratch& w = a.large;
+  const int32_t* srows = a.src_rows ? a.src_rows : a.rows;
+  const int tile = gemm_tile(w, n, d, PHI4_FP32, s);
+  const dim3 g((unsigned)(dz / 32), (unsigned)(dz / 32));
+  launch_irmh_mean(a.src, srows, n, d, q, a.done_ptr, s);
+  launch_irmh_inverse(A, d, q, a.done_ptr, s);
+  launch_irmh_whiten(a.src, srows, n, d, q, a.done_ptr, s);
+  lp_kernel<PHI4_FP32><<<g, 256, 0, s>>>(a.Bt, a.ldb, d, dz, w.lp, a.done_ptr);
+  for (int t = 0; t < a.n_steps; ++t) enqueue_step<PHI4_FP32>(a, w, tile, t, t == 0, s, &q);
+  if (a.prop) {
+    const hipError_t e = hipMemcpyAsync(a.prop, w.prop, sizeof(float) * (size_t)n * d,
+                                        hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return PHI4_EHIP;
+  }
+  acc_sum_kernel<<<1, 1024, 0, s>>>(w.accp, n, a.n_steps, a.acc_count, a.prop_count, a.done_ptr);
   return PHI4_OK;
 }
 
