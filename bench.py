@@ -70,6 +70,8 @@ def parse():
                          "run every run to beta = 1)")
     ap.add_argument("--only-extra", action="store_true",
                     help="run only the extra workloads and print them (profiling aid)")
+    ap.add_argument("--extra-match", default="", metavar="SUBSTR",
+                    help="with --only-extra: run only the extra workloads whose name contains SUBSTR")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MIB",
                     help="only copy MIB mebibytes device-to-device with torch and exit "
                          "(calibrates the HBM byte counters of a profiler run)")
@@ -132,9 +134,10 @@ def free_log_z(L, m2):
     return -0.5 * t
 
 
-def smc_workload(P, torch, L, N, m2, lam, n_steps, precision, seed=0):
+def smc_workload(P, torch, L, N, m2, lam, n_steps, precision, seed=0, kernel="rw"):
     """One warm-up run and one timed full SMC run (seed `seed`)."""
-    smc = P.SMC(L, N, m2, lam, ess_frac=0.5, n_steps=n_steps, seed=seed, precision=precision)
+    smc = P.SMC(L, N, m2, lam, ess_frac=0.5, n_steps=n_steps, seed=seed, precision=precision,
+                kernel=kernel)
     smc.restart(seed + 1000)
     smc.run()
     smc.restart(seed)
@@ -148,7 +151,7 @@ def smc_workload(P, torch, L, N, m2, lam, n_steps, precision, seed=0):
     kms, launches = P.phi4_kernel_time(smc.h)
     obs = smc.observables()
     out = dict(value=lv * N * n_steps / wall, levels=lv, ms_per_run=wall * 1e3,
-               logz=smc.logz(), mean_abs_m=obs["mean_abs_m"],
+               logz=smc.logz(), mean_abs_m=obs["mean_abs_m"], acc=obs["acc"],
                sweep_ms_per_level=kms / max(launches, 1))
     smc.close()
     return out
@@ -253,24 +256,40 @@ def paper_point(P, torch, sizes=(10, 15, 18), seed=0):
     return out
 
 
-def extra_workloads(P, torch):
-    """Free-theory check of the main workload, SMC at L = 16 and NS at L = 32."""
+def extra_workloads(P, torch, match=""):
+    """Free-theory check of the main workload, SMC-RW and SMC-IRMH at L = 16,
+    NS at L = 32 and the paper's own point; `match` keeps the names containing it."""
     ex = {}
-    progress("free-theory check")
-    fz = smc_workload(P, torch, 8, 4096, 1.0, 0.0, 20, "fp32")
-    exact = free_log_z(8, 1.0)
-    ex["free_theory_L8"] = dict(logz=fz["logz"], exact=exact, dlogz=fz["logz"] - exact,
-                                levels=fz["levels"], note="m2=1, lambda=0, N=4096, 20 steps/level; "
-                                "the gap is the method's finite-mixing bias, shared by the oracle")
+
+    def want(name):
+        return match in name
+
+    if want("free_theory_L8"):
+        progress("free-theory check")
+        fz = smc_workload(P, torch, 8, 4096, 1.0, 0.0, 20, "fp32")
+        exact = free_log_z(8, 1.0)
+        ex["free_theory_L8"] = dict(logz=fz["logz"], exact=exact, dlogz=fz["logz"] - exact,
+                                    levels=fz["levels"], note="m2=1, lambda=0, N=4096, 20 steps/"
+                                    "level; the gap is the method's finite-mixing bias, shared by "
+                                    "the oracle")
     for lam in (5.0, 8.0):
         for prec in ("fp32", "bf16"):
-            ex[f"smc_L16_N16384_lam{lam:g}_{prec}"] = smc_workload(P, torch, 16, 16384, -4.0, lam,
-                                                                     20, prec)
-            progress(f"SMC L=16 lambda={lam:g} {prec} done")
+            name = f"smc_L16_N16384_lam{lam:g}_{prec}"
+            if want(name):
+                ex[name] = smc_workload(P, torch, 16, 16384, -4.0, lam, 20, prec)
+                progress(f"SMC L=16 lambda={lam:g} {prec} done")
+    for L in (8, 16, 32):
+        name = f"smc_irmh_L{L}_N16384_lam8_fp32"
+        if want(name):
+            ex[name] = smc_workload(P, torch, L, 16384, -4.0, 8.0, 20, "fp32", kernel="irmh")
+            progress(f"SMC-IRMH L={L} done")
     for prec in ("fp32", "bf16"):
-        ex[f"ns_L32_n4096_k2048_{prec}"] = ns_workload(P, torch, 32, 4096, 2048, 40, prec, 8)
-        progress(f"NS L=32 {prec} done")
-    ex["paper_point_smc_rw"] = paper_point(P, torch)
+        name = f"ns_L32_n4096_k2048_{prec}"
+        if want(name):
+            ex[name] = ns_workload(P, torch, 32, 4096, 2048, 40, prec, 8)
+            progress(f"NS L=32 {prec} done")
+    if want("paper_point_smc_rw"):
+        ex["paper_point_smc_rw"] = paper_point(P, torch)
     return ex
 
 
@@ -302,8 +321,8 @@ def main():
         copy_probe(torch, args.copy_probe)
         return
     if args.only_extra:
-        ex = extra_workloads(P, torch)
-        if args.batch_levels > 0:
+        ex = extra_workloads(P, torch, args.extra_match)
+        if args.batch_levels > 0 and args.extra_match in "batch64":
             ex["batch64"] = batch_workload(P, torch, args.batch_levels)
         print(json.dumps({"workloads": ex}), flush=True)
         return

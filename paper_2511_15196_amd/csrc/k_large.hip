@@ -520,6 +520,128 @@ __global__ __launch_bounds__(kAT) void accept_kernel(AcceptArgs a) {
   }
 }
 
+// The same accept for d <= 256: one wave per particle, four particles per
+// workgroup (a 256-thread workgroup per particle leaves most lanes idle at
+// these sizes).  Every lane of a wave forms the same sums (DPP reduction)
+// and takes the same decision; lane 0 writes the per-particle outputs.
+constexpr int kAW = 4;   // particles (waves) per workgroup
+
+template <bool CONSTRAINED, int PER, bool IND>   // PER >= d / 64 sites per lane
+__global__ __launch_bounds__(64 * kAW) void accept_wave_kernel(AcceptArgs a) {
+  constexpr int NV = IND ? 7 : 6;
+  extern __shared__ __align__(16) float rowbuf[];   // kAW x d pairs (phi, phi')
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int p = blockIdx.x * kAW + wv;
+  const bool live = p < a.n;                      // uniform per wave
+  const int pc = live ? p : a.n - 1;
+  const int d = a.d, L = a.L;
+  const int cr = a.crows ? a.crows[pc] : pc;
+  const int orw = a.orows ? a.orows[pc] : pc;
+  float2* f = reinterpret_cast<float2*>(rowbuf) + (size_t)wv * d;
+  float zq = 0.f;
+  {
+    const float* cp = a.cur + (size_t)cr * d;
+    const float* pp = a.prop + (size_t)pc * d;
+    float vo[PER], vn[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int x = min(lane + i * 64, d - 1);
+      vo[i] = cp[x];
+      vn[i] = pp[x];
+    }
+    if (live && a.znext && !(a.done && *a.done)) {
+      const uint32_t c3p =
+          counter3((uint32_t)(a.level_ptr ? *a.level_ptr : a.level), PHI4_PROPOSE);
+      const int nq = a.dz / 4;
+      for (int q = lane; q < nq; q += 64) {
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (4 * q < d) {
+          v = normals4((uint32_t)q, (uint32_t)orw, a.step + 1, c3p, a.seed, a.run);
+          v.x *= a.zsign;
+          v.y *= a.zsign;
+          v.z *= a.zsign;
+          v.w *= a.zsign;
+        }
+        if constexpr (IND) zq += (v.x * v.x + v.y * v.y) + (v.z * v.z + v.w * v.w);
+        if (a.zprec == PHI4_FP32) {
+          *reinterpret_cast<float4*>(a.znext + (size_t)p * a.dz + 4 * q) = v;
+        } else {
+          ushort4 h;
+          h.x = to16(v.x, a.zprec);
+          h.y = to16(v.y, a.zprec);
+          h.z = to16(v.z, a.zprec);
+          h.w = to16(v.w, a.zprec);
+          *reinterpret_cast<ushort4*>(reinterpret_cast<unsigned short*>(a.znext) +
+                                      (size_t)p * a.dz + 4 * q) = h;
+          if (q == 0) a.zsgn[p] = h.x & 0x8000u;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i)
+      if (lane + i * 64 < d) f[lane + i * 64] = make_float2(vo[i], vn[i]);
+  }
+  __syncthreads();
+  float so = 0.f, sn = 0.f, ds = 0.f, du = 0.f, mo = 0.f, mn = 0.f;
+  const int cstep = 64 % L;
+  int col = lane % L;
+  const float hm2 = 0.5f * a.m2, lam = a.lam;
+  for (int x = lane; x < d; x += 64) {
+    const int y1 = col + 1 == L ? x + 1 - L : x + 1;
+    const int y0 = x + L < d ? x + L : x + L - d;
+    const float2 v = f[x], r1 = f[y1], r0 = f[y0];
+    const float a1o = r1.x - v.x, a0o = r0.x - v.x, f2o = v.x * v.x;
+    const float a1n = r1.y - v.y, a0n = r0.y - v.y, f2n = v.y * v.y;
+    const float to = 0.5f * (a1o * a1o + a0o * a0o) + hm2 * f2o + lam * f2o * f2o;
+    const float tn = 0.5f * (a1n * a1n + a0n * a0n) + hm2 * f2n + lam * f2n * f2n;
+    so += to;
+    sn += tn;
+    ds += tn - to;
+    du += 0.5f * (f2n - f2o);
+    mo += v.x;
+    mn += v.y;
+    col += cstep;
+    if (col >= L) col -= L;
+  }
+  float v[NV];
+  v[0] = so;
+  v[1] = sn;
+  v[2] = ds;
+  v[3] = du;
+  v[4] = mo;
+  v[5] = mn;
+  if constexpr (IND) v[6] = zq;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = wave_sum_f(v[q]);
+  const bool frozen = a.reject_all || (a.done && *a.done);
+  const uint32_t c3a = counter3((uint32_t)(a.level_ptr ? *a.level_ptr : a.level), PHI4_ACCEPT);
+  const float lu = __logf(u01(word0((uint32_t)orw, a.step, c3a, a.seed, a.run)));
+  int acc;
+  if constexpr (!CONSTRAINED) {
+    const float beta = a.beta_ptr ? (float)(*a.beta_ptr) : a.beta;
+    if constexpr (IND)
+      acc = lu < -v[3] - beta * v[2] + 0.5f * (a.zz_in[pc] - a.r[pc]);
+    else
+      acc = lu < -v[3] - beta * v[2];
+  } else {
+    const float sstar = a.sstar_ptr ? *a.sstar_ptr : a.s_star;
+    acc = (v[1] < sstar) && (lu < -v[3] * a.inv_prior_var);
+  }
+  if (frozen) acc = 0;
+  if (live && lane == 0) {
+    if constexpr (IND) {
+      if (acc) a.r[p] = a.zz_in[p];
+      if (a.znext) a.zz_out[p] = v[6];
+    }
+    a.S[orw] = acc ? v[1] : v[0];
+    if (a.absM) a.absM[orw] = fabsf((acc ? v[5] : v[4]) / d);
+    if (a.accp && !frozen) a.accp[p] += acc;
+    if (a.acc_flags) a.acc_flags[p] = (uint8_t)acc;
+  }
+  if (live && (acc || a.copy_rejected))
+    for (int x = lane; x < d; x += 64) a.dst[(size_t)orw * d + x] = acc ? f[x].y : f[x].x;
+}
+
 // Sums the per-slot acceptance counts into the run's counters and clears them.
 __global__ __launch_bounds__(1024) void acc_sum_kernel(int32_t* accp, int n, int nsteps,
                                                        unsigned long long* acc_count,
@@ -585,6 +707,17 @@ void launch_gemm(int tile, const LargeScratch& w, const float* cur, const int32_
 template <bool CONSTRAINED, bool IND = false>
 void launch_accept(int per, int n, size_t lds, const AcceptArgs& aa, hipStream_t st) {
   static_assert(PHI4_MAX_SITES <= 16 * kAT, "accept stages at most 16 sites per thread");
+  if (aa.d <= 256) {   // one wave per particle
+    const unsigned g = (unsigned)((n + kAW - 1) / kAW);
+    const size_t wl = kAW * 2 * (size_t)aa.d * sizeof(float);
+    if (aa.d <= 64)
+      accept_wave_kernel<CONSTRAINED, 1, IND><<<g, 64 * kAW, wl, st>>>(aa);
+    else if (aa.d <= 128)
+      accept_wave_kernel<CONSTRAINED, 2, IND><<<g, 64 * kAW, wl, st>>>(aa);
+    else
+      accept_wave_kernel<CONSTRAINED, 4, IND><<<g, 64 * kAW, wl, st>>>(aa);
+    return;
+  }
   if (per <= 2)
     accept_kernel<CONSTRAINED, 2, IND><<<n, kAT, lds, st>>>(aa);
   else if (per <= 4)
