@@ -22,6 +22,8 @@ Each function cites the passage of the paper it follows:
                    Monte Carlo methods" (i), App. A).
 * ``irmh``      -- the same tempered SMC with an independent Metropolis-Hastings
                    proposal fitted to the particles (Sec. 2 (ii), App. A).
+* ``hmc``       -- the same tempered SMC with Hamiltonian Monte Carlo
+                   trajectories, diagonal mass (Sec. 2 (iii), App. A).
 * ``ns``        -- nested sampling with likelihood-constrained random-walk
                    refill (Sec. 2 (iv), App. A).
 * ``precision`` -- round-to-nearest-even emulation of the reduced-precision
@@ -30,4 +32,4 @@ Each function cites the passage of the paper it follows:
 Parity status of every function is listed in each module's header.
 """
 
-from . import rng, action, precision, smc, irmh, ns  # noqa: F401
+from . import rng, action, precision, smc, irmh, hmc, ns  # noqa: F401
