@@ -68,12 +68,19 @@ enum { PHI4_INIT = 1, PHI4_PROPOSE = 2, PHI4_ACCEPT = 3, PHI4_RESAMPLE = 4, PHI4
  *   of the resampled particles, log alpha = -dU0 - beta dS + (|z|^2 - r) / 2
  *   with r = |L^{-1}(phi - mu)|^2 of the current particle.  float32 only,
  *   d <= PHI4_IRMH_MAX_SITES; eps0 and acc_target are unused (the eps that
- *   phi4_observables reports is then meaningless). */
-enum { PHI4_KERNEL_RW = 0, PHI4_KERNEL_IRMH = 1 };
+ *   phi4_observables reports is then meaningless).
+ * PHI4_KERNEL_HMC: Hamiltonian Monte Carlo (Sec. 2 (iii); App. A),
+ *   n_leapfrog leapfrog steps per trajectory on V = U0 + beta S with the
+ *   diagonal mass diag(1 / v), v the site variances of the resampled
+ *   particles; momentum p = z / sqrt(v) with z from the PROPOSE stream;
+ *   accept iff log u < -(H' - H).  eps0 <= 0 selects d^(-1/4); eps is
+ *   steered to acc_target like the random walk's.  float32 only; the
+ *   covariance is formed but not factorised. */
+enum { PHI4_KERNEL_RW = 0, PHI4_KERNEL_IRMH = 1, PHI4_KERNEL_HMC = 2 };
 #define PHI4_IRMH_MAX_SITES 1024
 
 /* One adaptive tempered SMC run (Sec. 2 "Particle-based Monte Carlo
- * methods" (i), (ii); App. A).  Target p_beta ~ exp(-[U0 + beta S]) with
+ * methods" (i) - (iii); App. A).  Target p_beta ~ exp(-[U0 + beta S]) with
  * U0 = |phi|^2 / 2 and S the action of Sec. 2 Eq. (1); log Z estimates
  * log E_{phi ~ N(0, I)}[exp(-S(phi))]. */
 typedef struct phi4_smc_config {
@@ -88,7 +95,8 @@ typedef struct phi4_smc_config {
   uint32_t seed;        /* Philox key word 0 */
   uint32_t run;         /* Philox key word 1 */
   int32_t precision;    /* PHI4_FP32 / PHI4_BF16 / PHI4_FP16 */
-  int32_t kernel;       /* inner kernel: PHI4_KERNEL_RW (0) or PHI4_KERNEL_IRMH (1) */
+  int32_t kernel;       /* inner kernel: PHI4_KERNEL_RW (0), _IRMH (1) or _HMC (2) */
+  int32_t n_leapfrog;   /* HMC: leapfrog steps per trajectory, 0 selects 20 (App. A), <= 1000 */
 } phi4_smc_config;
 
 /* One nested-sampling run (Sec. 2 (iv); App. A) with a likelihood-

@@ -41,8 +41,7 @@ import numpy as np
 
 from . import rng
 from .action import action, magnetisation, u0
-from .smc import (adapt_eps, covariance, ess, init_particles, reweight,
-                  systematic_resample)
+from .smc import adapt_eps, ess, init_particles, reweight, systematic_resample
 
 
 def grad_action(phi, L, m2, lam):
@@ -105,8 +104,10 @@ def default_eps0(d):
 
 
 def smc_run(L, m2, lam, N, ess_frac=0.5, n_steps=5, seed=0, run=0, n_leap=20,
-            acc_target=0.65, eps0=None, max_levels=100000, keep_particles=False):
-    """Adaptive tempered SMC-HMC from beta = 0 to beta = 1."""
+            acc_target=0.65, eps0=None, max_levels=100000, keep_particles=False,
+            stop_after=None):
+    """Adaptive tempered SMC-HMC from beta = 0 to beta = 1 (or, with
+    `stop_after`, the state after that many levels)."""
     d = L * L
     eps0 = default_eps0(d) if eps0 is None or eps0 <= 0 else eps0
     eps = eps0
@@ -116,7 +117,7 @@ def smc_run(L, m2, lam, N, ess_frac=0.5, n_steps=5, seed=0, run=0, n_leap=20,
     logz = 0.0
     levels = []
     level = 0
-    while beta < 1.0:
+    while beta < 1.0 and (stop_after is None or level < stop_after):
         level += 1
         if level > max_levels:
             raise RuntimeError("too many tempering levels")
@@ -126,7 +127,7 @@ def smc_run(L, m2, lam, N, ess_frac=0.5, n_steps=5, seed=0, run=0, n_leap=20,
         anc = systematic_resample(w, rng.resample_word(seed, run, level))
         phi = phi[anc]
         S = S[anc]
-        v = np.diag(covariance(phi)).copy()
+        v = phi.var(axis=0, ddof=1)   # the covariance's diagonal, divisor N - 1
         beta = new_beta
         n_acc = 0
         for s in range(n_steps):

@@ -15,7 +15,7 @@ from . import _abi
 from ._abi import (  # noqa: F401
     PHI4_OK, PHI4_DONE, PHI4_EINVAL, PHI4_EHIP, PHI4_ECHOL, PHI4_ENONFINITE,
     PHI4_FP32, PHI4_BF16, PHI4_FP16, PHI4_INIT, PHI4_PROPOSE, PHI4_ACCEPT,
-    PHI4_RESAMPLE, PHI4_NS_PICK, PHI4_MAX_SITES, PHI4_KERNEL_RW, PHI4_KERNEL_IRMH,
+    PHI4_RESAMPLE, PHI4_NS_PICK, PHI4_MAX_SITES, PHI4_KERNEL_RW, PHI4_KERNEL_IRMH, PHI4_KERNEL_HMC,
     PHI4_IRMH_MAX_SITES, KERNELS, Phi4Error, SmcConfig, NsConfig, lib, library_path,
 )
 
@@ -264,12 +264,16 @@ def phi4_mutate(src, dst, n, L, m2, lam, Bt, kind, beta, s_star, prior_var, seed
 class SMC:
     """One adaptive tempered SMC run with torch-owned device buffers."""
 
-    def __init__(self, L, N, m2, lam, ess_frac=0.5, n_steps=10, acc_target=0.3, eps0=0.0,
-                 seed=0, run=0, precision="fp32", sweep="auto", device="cuda", kernel="rw"):
+    def __init__(self, L, N, m2, lam, ess_frac=0.5, n_steps=10, acc_target=None, eps0=0.0,
+                 seed=0, run=0, precision="fp32", sweep="auto", device="cuda", kernel="rw",
+                 n_leapfrog=20):
         import torch
+        if acc_target is None:   # HMC is steered to a higher acceptance than the random walk
+            acc_target = 0.65 if kernel == "hmc" else 0.3
         self.cfg = SmcConfig(L=L, N=N, m2=m2, lambda_=lam, ess_frac=ess_frac, n_steps=n_steps,
                              acc_target=acc_target, eps0=eps0, seed=seed, run=run,
-                             precision=PRECISIONS[precision], kernel=KERNELS[kernel])
+                             precision=PRECISIONS[precision], kernel=KERNELS[kernel],
+                             n_leapfrog=n_leapfrog)
         nbytes = smc_workspace_bytes(self.cfg)
         if nbytes == 0:
             raise Phi4Error(PHI4_EINVAL, "invalid SMC configuration")

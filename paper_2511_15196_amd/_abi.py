@@ -8,9 +8,9 @@ PHI4_EINVAL, PHI4_EHIP, PHI4_ECHOL, PHI4_ENONFINITE = -1, -2, -3, -4
 PHI4_FP32, PHI4_BF16, PHI4_FP16 = 0, 1, 2
 PHI4_INIT, PHI4_PROPOSE, PHI4_ACCEPT, PHI4_RESAMPLE, PHI4_NS_PICK = 1, 2, 3, 4, 5
 PHI4_MAX_SITES = 4096
-PHI4_KERNEL_RW, PHI4_KERNEL_IRMH = 0, 1
+PHI4_KERNEL_RW, PHI4_KERNEL_IRMH, PHI4_KERNEL_HMC = 0, 1, 2
 PHI4_IRMH_MAX_SITES = 1024
-KERNELS = {"rw": PHI4_KERNEL_RW, "irmh": PHI4_KERNEL_IRMH}
+KERNELS = {"rw": PHI4_KERNEL_RW, "irmh": PHI4_KERNEL_IRMH, "hmc": PHI4_KERNEL_HMC}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libphi4pmc.so")
@@ -36,6 +36,7 @@ class SmcConfig(ctypes.Structure):
         ("run", ctypes.c_uint32),
         ("precision", ctypes.c_int32),
         ("kernel", ctypes.c_int32),
+        ("n_leapfrog", ctypes.c_int32),
     ]
 
 

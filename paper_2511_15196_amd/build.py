@@ -18,8 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libphi4pmc.so")
 
-SOURCES = ["k_field.hip", "k_mutate.hip", "k_large.hip", "k_irmh.hip", "k_reweight.hip", "k_factor.hip",
-           "k_ns.hip", "abi.cpp"]
+SOURCES = ["k_field.hip", "k_mutate.hip", "k_large.hip", "k_irmh.hip", "k_hmc.hip", "k_reweight.hip",
+           "k_factor.hip", "k_ns.hip", "abi.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950",

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "hmc.hpp"
 #include "irmh.hpp"
 
 using namespace phi4;
@@ -56,6 +57,13 @@ struct Carver {
 };
 
 double default_eps0(int d, double eps0) { return eps0 > 0 ? eps0 : 2.38 / std::sqrt((double)d); }
+
+// HMC: d^(-1/4), the dimension scaling of leapfrog steps
+double smc_eps0(const phi4_smc_config& c) {
+  const int d = c.L * c.L;
+  if (c.kernel == PHI4_KERNEL_HMC) return c.eps0 > 0 ? c.eps0 : std::pow((double)d, -0.25);
+  return default_eps0(d, c.eps0);
+}
 
 // Scratch of the three-pass sweep for n particles.
 LargeScratch take_large(Carver& cv, int n, int d) {
@@ -138,8 +146,13 @@ bool smc_valid(const phi4_smc_config* c, std::string* why) {
   if (c->n_steps < 0) return *why = "n_steps must be >= 0", false;
   if (!std::isfinite(c->m2) || !std::isfinite(c->lambda)) return *why = "couplings must be finite", false;
   if (!mutate_supported((int)d, c->precision)) return *why = "unsupported precision", false;
-  if (c->kernel != PHI4_KERNEL_RW && c->kernel != PHI4_KERNEL_IRMH)
+  if (c->kernel != PHI4_KERNEL_RW && c->kernel != PHI4_KERNEL_IRMH &&
+      c->kernel != PHI4_KERNEL_HMC)
     return *why = "unknown inner kernel", false;
+  if (c->kernel == PHI4_KERNEL_HMC && c->precision != PHI4_FP32)
+    return *why = "the HMC kernel runs in float32 only", false;
+  if (c->kernel == PHI4_KERNEL_HMC && (c->n_leapfrog < 0 || c->n_leapfrog > 1000))
+    return *why = "n_leapfrog must be in [0, 1000]", false;
   if (c->kernel == PHI4_KERNEL_IRMH && c->precision != PHI4_FP32)
     return *why = "the independence sampler runs in float32 only", false;
   if (c->kernel == PHI4_KERNEL_IRMH && d > PHI4_IRMH_MAX_SITES)
@@ -278,8 +291,10 @@ int enqueue_reweight(Handle* h, SmcState* mirror = nullptr) {
   fa.A = b.A;
   fa.Bt = b.Bt;
   fa.ldb = h->d;
-  // the independence sampler proposes with L itself
+  // the independence sampler proposes with L itself; HMC needs only the
+  // covariance's diagonal (no factor)
   fa.eps_ptr = h->smc.kernel == PHI4_KERNEL_IRMH ? b.irmh.one : &b.st->eps;
+  fa.cov_only = h->smc.kernel == PHI4_KERNEL_HMC;
   fa.tau_out = &b.st->tau;
   fa.err_out = &b.st->err;
   fa.done = &b.st->done;
@@ -319,13 +334,38 @@ int enqueue_mutate(Handle* h) {
   m.absM = b.absM;
   m.acc_count = &b.st->acc;
   m.prop_count = &b.st->prop;
-  int rc;
+  int rc = PHI4_OK;
   {
     TimedLaunch tl(h);
-    if (h->smc.kernel == PHI4_KERNEL_IRMH)
+    if (h->smc.kernel == PHI4_KERNEL_IRMH) {
       rc = launch_irmh_sweep(m, b.A, b.irmh, h->stream);
-    else
+    } else if (h->smc.kernel == PHI4_KERNEL_HMC) {
+      HmcArgs ha = {};
+      ha.src = m.src;
+      ha.src_rows = m.src_rows;
+      ha.dst = m.dst;
+      ha.n = h->n;
+      ha.L = h->L;
+      ha.d = h->d;
+      ha.m2 = h->m2;
+      ha.lam = h->lam;
+      ha.beta_ptr = &b.st->beta;
+      ha.eps_ptr = &b.st->eps;
+      ha.sigma = b.sigma;
+      ha.n_leap = h->smc.n_leapfrog > 0 ? h->smc.n_leapfrog : 20;
+      ha.n_steps = h->n_steps;
+      ha.seed = h->seed;
+      ha.run = h->run;
+      ha.level_ptr = &b.st->level;
+      ha.done = &b.st->done;
+      ha.S = m.S;
+      ha.absM = m.absM;
+      ha.acc_count = m.acc_count;
+      ha.prop_count = m.prop_count;
+      launch_hmc_sweep(ha, h->stream);
+    } else {
       rc = launch_mutate(m, h->precision, h->stream);
+    }
   }
   if (rc) return fail(rc, "smc_mutate: unsupported shape");
   h->cur ^= 1;
@@ -532,7 +572,7 @@ int smc_init(const phi4_smc_config* cfg, float* phi, float* S, void* workspace,
     delete h;
     return rc;
   }
-  launch_smc_state_init(h->sb.st, default_eps0(h->d, cfg->eps0), cfg->acc_target, cfg->ess_frac,
+  launch_smc_state_init(h->sb.st, smc_eps0(*cfg), cfg->acc_target, cfg->ess_frac,
                         h->stream);
   launch_init_fields(phi, S, h->sb.absM, h->n, h->L, h->m2, h->lam, 1.0f, h->seed, h->run,
                      h->stream);
@@ -554,7 +594,7 @@ int smc_restart(void* handle, uint32_t seed, uint32_t run) {
   h->smc.run = run;
   h->cur = 0;
   h->anc_pending = false;
-  launch_smc_state_init(h->sb.st, default_eps0(h->d, h->smc.eps0), h->smc.acc_target,
+  launch_smc_state_init(h->sb.st, smc_eps0(h->smc), h->smc.acc_target,
                         h->smc.ess_frac, h->stream);
   launch_init_fields(h->phi, h->S, h->sb.absM, h->n, h->L, h->m2, h->lam, 1.0f, seed, run,
                      h->stream);

@@ -67,8 +67,9 @@ def test_workspace_sizes_and_validation():
                        acc_target=0.3, eps0=0.0, seed=0, run=0, precision=0)
     assert P.smc_workspace_bytes(good) > 4096 * 64 * 4
     for bad in [dict(L=65), dict(N=1), dict(ess_frac=0.0), dict(ess_frac=1.5), dict(precision=7),
-                dict(n_steps=-1), dict(kernel=2), dict(kernel=1, precision=1),
-                dict(kernel=1, L=33)]:
+                dict(n_steps=-1), dict(kernel=3), dict(kernel=1, precision=1),
+                dict(kernel=1, L=33), dict(kernel=2, precision=1), dict(kernel=2, n_leapfrog=-1),
+                dict(kernel=2, n_leapfrog=1001)]:
         cfg = P.SmcConfig(**{**{f: getattr(good, f) for f, _ in good._fields_}, **bad})
         assert P.smc_workspace_bytes(cfg) == 0
     # the independence sampler adds its own scratch (mean, whitening factor, residuals)
@@ -76,6 +77,10 @@ def test_workspace_sizes_and_validation():
     assert P.smc_workspace_bytes(ind) > P.smc_workspace_bytes(good) + 64 * 64 * 4
     ind.L = 32
     assert P.smc_workspace_bytes(ind) > 0
+    hmc = P.SmcConfig(**{**{f: getattr(good, f) for f, _ in good._fields_}, "kernel": 2})
+    assert P.smc_workspace_bytes(hmc) == P.smc_workspace_bytes(good)
+    hmc.L, hmc.n_leapfrog = 64, 1000
+    assert P.smc_workspace_bytes(hmc) > 0
     ns = P.NsConfig(L=8, n_live=4096, k_delete=2048, n_steps=40, m2=-4.0, lambda_=8.0,
                     prior_var=4.0, term_frac=1e-3, acc_target=0.3, eps0=0.0, seed=0, run=0,
                     precision=1)
