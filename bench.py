@@ -257,8 +257,9 @@ def paper_point(P, torch, sizes=(10, 15, 18), seed=0):
 
 
 def extra_workloads(P, torch, match=""):
-    """Free-theory check of the main workload, SMC-RW and SMC-IRMH at L = 16,
-    NS at L = 32 and the paper's own point; `match` keeps the names containing it."""
+    """Free-theory check of the main workload, SMC-RW, SMC-IRMH and SMC-HMC at
+    L = 8 .. 32, NS at L = 32 and the paper's own point; `match` keeps the
+    names containing it."""
     ex = {}
 
     def want(name):
@@ -283,6 +284,15 @@ def extra_workloads(P, torch, match=""):
         if want(name):
             ex[name] = smc_workload(P, torch, L, 16384, -4.0, 8.0, 20, "fp32", kernel="irmh")
             progress(f"SMC-IRMH L={L} done")
+    for L in (8, 16, 32):
+        name = f"smc_hmc_L{L}_N16384_lam8_fp32"
+        if want(name):
+            r = smc_workload(P, torch, L, 16384, -4.0, 8.0, 5, "fp32", kernel="hmc")
+            # one particle-update = one 20-step trajectory; a leapfrog step evaluates
+            # the gradient at every site once
+            r["gradient_site_evals_per_s"] = r["value"] * 20 * L * L
+            ex[name] = r
+            progress(f"SMC-HMC L={L} done")
     for prec in ("fp32", "bf16"):
         name = f"ns_L32_n4096_k2048_{prec}"
         if want(name):

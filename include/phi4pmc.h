@@ -74,8 +74,8 @@ enum { PHI4_INIT = 1, PHI4_PROPOSE = 2, PHI4_ACCEPT = 3, PHI4_RESAMPLE = 4, PHI4
  *   diagonal mass diag(1 / v), v the site variances of the resampled
  *   particles; momentum p = z / sqrt(v) with z from the PROPOSE stream;
  *   accept iff log u < -(H' - H).  eps0 <= 0 selects d^(-1/4); eps is
- *   steered to acc_target like the random walk's.  float32 only; the
- *   covariance is formed but not factorised. */
+ *   steered to acc_target like the random walk's.  float32 only; each
+ *   level forms the site variances only (no covariance, no factor). */
 enum { PHI4_KERNEL_RW = 0, PHI4_KERNEL_IRMH = 1, PHI4_KERNEL_HMC = 2 };
 #define PHI4_IRMH_MAX_SITES 1024
 

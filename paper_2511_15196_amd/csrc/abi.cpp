@@ -94,6 +94,8 @@ struct SmcBufs {
   int32_t* bstatus;
   double* bscr;
   IrmhScratch irmh;   // independence sampler only
+  double* hvar;       // HMC only: site variances (d) and their partial sums
+  double* hpart;
 };
 
 // Blocked-factor fields of FactorArgs from its carved scratch.
@@ -129,6 +131,11 @@ size_t smc_carve(const phi4_smc_config& c, void* ws, SmcBufs* b) {
   t.bstatus = cv.take<int32_t>(kJitterAttempts + 1);
   t.bscr = cv.take<double>(blocked_scratch_doubles(d));
   t.irmh = IrmhScratch{};
+  t.hvar = t.hpart = nullptr;
+  if (c.kernel == PHI4_KERNEL_HMC) {
+    t.hvar = cv.take<double>(d);
+    t.hpart = cv.take<double>((size_t)2 * site_var_chunks(n) * d);
+  }
   if (c.kernel == PHI4_KERNEL_IRMH) {
     char* base = cv.take<char>(irmh_scratch_bytes(n, d));
     if (cv.base) t.irmh = irmh_scratch(base, n, d);
@@ -283,6 +290,11 @@ int enqueue_reweight(Handle* h, SmcState* mirror = nullptr) {
   ra.anc = b.anc;
   launch_reweight(ra, h->stream);
   h->anc_pending = true;
+  if (h->smc.kernel == PHI4_KERNEL_HMC) {
+    // the diagonal mass needs the site variances only
+    launch_site_variance(cur_phi(h), b.anc, h->n, h->d, b.hpart, b.hvar, &b.st->done, h->stream);
+    return hip_check("smc_reweight_resample");
+  }
   launch_cov_partials(cur_phi(h), b.anc, h->plan, b.part, &b.st->done, h->stream);
   FactorArgs fa = {};
   fa.part = b.part;
@@ -291,10 +303,8 @@ int enqueue_reweight(Handle* h, SmcState* mirror = nullptr) {
   fa.A = b.A;
   fa.Bt = b.Bt;
   fa.ldb = h->d;
-  // the independence sampler proposes with L itself; HMC needs only the
-  // covariance's diagonal (no factor)
+  // the independence sampler proposes with L itself
   fa.eps_ptr = h->smc.kernel == PHI4_KERNEL_IRMH ? b.irmh.one : &b.st->eps;
-  fa.cov_only = h->smc.kernel == PHI4_KERNEL_HMC;
   fa.tau_out = &b.st->tau;
   fa.err_out = &b.st->err;
   fa.done = &b.st->done;
@@ -351,7 +361,7 @@ int enqueue_mutate(Handle* h) {
       ha.lam = h->lam;
       ha.beta_ptr = &b.st->beta;
       ha.eps_ptr = &b.st->eps;
-      ha.sigma = b.sigma;
+      ha.var = b.hvar;
       ha.n_leap = h->smc.n_leapfrog > 0 ? h->smc.n_leapfrog : 20;
       ha.n_steps = h->n_steps;
       ha.seed = h->seed;

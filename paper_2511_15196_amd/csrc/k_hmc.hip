@@ -50,7 +50,7 @@ __global__ __launch_bounds__(NT) void hmc_kernel(HmcArgs a) {
     n3[i] = xc + L < d ? xc + L : xc + L - d;
     n4[i] = xc >= L ? xc - L : xc - L + d;
     f0[i] = a.src[(size_t)srow * d + xc];
-    var[i] = (float)a.sigma[(size_t)xc * d + xc];
+    var[i] = (float)a.var[xc];
     sd[i] = sqrtf(var[i]);
   }
 
@@ -177,7 +177,66 @@ __global__ __launch_bounds__(NT) void hmc_kernel(HmcArgs a) {
   }
 }
 
+constexpr int kVarRows = 64;
+
+// Column tile x (64 sites) and row chunk y: sums of (phi - c) and
+// (phi - c)^2 over the chunk's rows, c the first row's value (float64).
+__global__ __launch_bounds__(256) void var_partial_kernel(const float* __restrict__ phi,
+                                                          const int32_t* __restrict__ rows, int n,
+                                                          int d, double* __restrict__ part,
+                                                          const int32_t* __restrict__ done) {
+  if (done && *done) return;
+  __shared__ double sh[2][4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int x = blockIdx.x * 64 + lane, xc = min(x, d - 1);
+  const int r0 = blockIdx.y * kVarRows, r1 = min(n, r0 + kVarRows);
+  const double c = (double)phi[(size_t)(rows ? rows[0] : 0) * d + xc];
+  double s1 = 0.0, s2 = 0.0;
+#pragma unroll 4
+  for (int i = r0 + wv; i < r1; i += 4) {
+    const double y = (double)phi[(size_t)(rows ? rows[i] : i) * d + xc] - c;
+    s1 += y;
+    s2 += y * y;
+  }
+  sh[0][wv][lane] = s1;
+  sh[1][wv][lane] = s2;
+  __syncthreads();
+  if (wv == 0 && x < d) {
+    const size_t o = (size_t)blockIdx.y * d + x, half = (size_t)gridDim.y * d;
+    part[o] = (sh[0][0][lane] + sh[0][1][lane]) + (sh[0][2][lane] + sh[0][3][lane]);
+    part[half + o] = (sh[1][0][lane] + sh[1][1][lane]) + (sh[1][2][lane] + sh[1][3][lane]);
+  }
+}
+
+// One wave per site: lanes take the chunks lane, lane + 64, ..., then a
+// fixed-order wave sum.
+__global__ __launch_bounds__(256) void var_final_kernel(const double* __restrict__ part, int chunks,
+                                                        int n, int d, double* __restrict__ var,
+                                                        const int32_t* __restrict__ done) {
+  if (done && *done) return;
+  const int x = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (x >= d) return;   // whole waves
+  double s1 = 0.0, s2 = 0.0;
+  for (int b = lane; b < chunks; b += 64) {
+    s1 += part[(size_t)b * d + x];
+    s2 += part[(size_t)(chunks + b) * d + x];
+  }
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  if (lane == 0) var[x] = (s2 - s1 * s1 / n) / (n - 1);
+}
+
 }  // namespace
+
+int site_var_chunks(int n) { return (n + kVarRows - 1) / kVarRows; }
+
+void launch_site_variance(const float* phi, const int32_t* rows, int n, int d, double* part,
+                          double* var, const int32_t* done, hipStream_t s) {
+  const int chunks = site_var_chunks(n);
+  var_partial_kernel<<<dim3((unsigned)((d + 63) / 64), (unsigned)chunks), 256, 0, s>>>(
+      phi, rows, n, d, part, done);
+  var_final_kernel<<<(unsigned)((d + 3) / 4), 256, 0, s>>>(part, chunks, n, d, var, done);
+}
 
 void launch_hmc_sweep(const HmcArgs& a, hipStream_t s) {
   if (a.n <= 0) return;

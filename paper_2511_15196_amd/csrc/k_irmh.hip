@@ -6,8 +6,8 @@
 // cloud can be nearly degenerate (condition numbers of 1e6 .. 1e10 at a few
 // particles per site), so r is formed in float64 throughout:
 //
-//   mean:     column sums in float64, chunks of 256 rows, then the chunks
-//             in a fixed order (deterministic);
+//   mean:     column sums in float64, chunks of 64 rows, then the chunks
+//             by one wave per column in a fixed order (deterministic);
 //   inverse:  column j of L^{-1} by forward substitution in float64, one
 //             wave per column, the column's entries in registers (lane m % 64,
 //             slot m / 64) and the rows of L prefetched several rows ahead;
@@ -22,7 +22,7 @@ namespace phi4 {
 
 namespace {
 
-constexpr int kMeanRows = 256;
+constexpr int kMeanRows = 64;
 constexpr int kWT = 64;   // whitening tile: particles x columns
 constexpr int kWK = 16;   // K chunk
 
@@ -41,6 +41,7 @@ __global__ __launch_bounds__(256) void mean_partial_kernel(const float* __restri
   const int r0 = blockIdx.y * kMeanRows, r1 = min(n, r0 + kMeanRows);
   double s = 0.0;
   if (c < d)
+#pragma unroll 4
     for (int i = r0 + wv; i < r1; i += 4) {
       const int r = rows ? rows[i] : i;
       s += (double)phi[(size_t)r * d + c];
@@ -57,12 +58,15 @@ __global__ __launch_bounds__(256) void mean_final_kernel(const double* __restric
                                                          double* __restrict__ mu64,
                                                          const int32_t* __restrict__ done) {
   if (done && *done) return;
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c >= d) return;
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (c >= d) return;   // whole waves
   double s = 0.0;
-  for (int b = 0; b < chunks; ++b) s += part[(size_t)b * d + c];
-  mu64[c] = s / n;
-  mu[c] = (float)(s / n);
+  for (int b = lane; b < chunks; b += 64) s += part[(size_t)b * d + c];
+  s = wave_sum(s);
+  if (lane == 0) {
+    mu64[c] = s / n;
+    mu[c] = (float)(s / n);
+  }
 }
 
 // Column j of L^{-1}: x_0 = 1 / L[j][j], x_m = -(sum_{k < m} L[j+m][j+k] x_k)
@@ -246,7 +250,7 @@ void launch_irmh_mean(const float* phi, const int32_t* rows, int n, int d, const
   const int chunks = irmh_mean_chunks(n);
   mean_partial_kernel<<<dim3((unsigned)((d + 63) / 64), (unsigned)chunks), 256, 0, s>>>(
       phi, rows, n, d, q.mpart, done);
-  mean_final_kernel<<<(d + 255) / 256, 256, 0, s>>>(q.mpart, chunks, n, d, q.mu, q.mu64, done);
+  mean_final_kernel<<<(d + 3) / 4, 256, 0, s>>>(q.mpart, chunks, n, d, q.mu, q.mu64, done);
 }
 
 void launch_irmh_inverse(const double* A, int d, const IrmhScratch& q, const int32_t* done,

@@ -78,7 +78,7 @@ def test_workspace_sizes_and_validation():
     ind.L = 32
     assert P.smc_workspace_bytes(ind) > 0
     hmc = P.SmcConfig(**{**{f: getattr(good, f) for f, _ in good._fields_}, "kernel": 2})
-    assert P.smc_workspace_bytes(hmc) == P.smc_workspace_bytes(good)
+    assert P.smc_workspace_bytes(hmc) > P.smc_workspace_bytes(good)   # site variances
     hmc.L, hmc.n_leapfrog = 64, 1000
     assert P.smc_workspace_bytes(hmc) > 0
     ns = P.NsConfig(L=8, n_live=4096, k_delete=2048, n_steps=40, m2=-4.0, lambda_=8.0,
