@@ -6,9 +6,11 @@ App. A): nested sampling keeps a population of live points, deletes a fraction
 of them per iteration (0.5 in the paper's settings), and refills the deleted
 slots with MCMC moves that must satisfy the current likelihood constraint; the
 inner kernel is tuned by the particle covariance.  The paper's own refill is
-slice sampling; here the refill is a likelihood-constrained Gaussian random
-walk with the same covariance preconditioning (the paper's random-walk kernel
-of App. A under the NS constraint).
+slice sampling (``refill="slice"``: hit-and-run slice moves along directions
+from the survivors' covariance, Neal's stepping-out and shrinkage); the
+default refill is a likelihood-constrained Gaussian random walk with the same
+covariance preconditioning (the paper's random-walk kernel of App. A under the
+NS constraint).
 
 Readings taken where the paper is silent:
 
@@ -32,7 +34,10 @@ Readings taken where the paper is silent:
 
 Parity status: pinned by tests/test_oracle_ns.py against the closed-form
 free-theory evidence -1/2 sum_k log(1 + prior_var (m^2 + lambda_k)) and the
-exact prior-volume sequence; at interacting couplings "parity unpinned" beyond
+exact prior-volume sequence; the slice refill by tests/test_oracle_ns_slice.py
+(invariance of the prior and of the truncated-normal constrained prior at
+L = 1, also with brackets ten times the slice, the constraint on a lattice,
+free-theory and 2 x 2 quadrature evidences); at interacting couplings "parity unpinned" beyond
 the statistical comparison (see the design notes).
 """
 
@@ -80,10 +85,64 @@ def constrained_step(phi, B, S_star, prior_var, L, m2, lam, seed, run, it, step,
     return new_phi, acc, S_prop
 
 
+# Slice-sampling refill (Sec. 2 (iv); App. A: the paper's own NS kernel):
+# hit-and-run slice sampling of the prior restricted to the likelihood
+# constraint, along a direction drawn from the survivors' covariance, with
+# Neal's stepping-out (limit m) and shrinkage procedures (Neal, "Slice
+# sampling", Ann. Statist. 2003).
+SLICE_WIDTH = 1.0       # w, in units of the direction L z
+SLICE_MAX_STEPS = 32    # m: at most m - 1 expansions in total
+SLICE_MAX_SHRINK = 64   # shrinkage draws; if all miss, the point stays
+
+
+def slice_move(phi, u, S_cur, S_star, prior_var, L, m2, lam, uniforms):
+    """One slice move of the field phi (1-D) along direction u.
+
+    The slice of t -> N(phi + t u; 0, prior_var I) restricted to
+    S(phi + t u) < S_star at the level log y = log prior(phi) + log U0;
+    uniforms(j) is the j-th uniform of the move (U0, then the initial offset,
+    the step-out split, then one per shrinkage draw).  Returns (phi', S')."""
+    phi = np.asarray(phi, dtype=np.float64)
+    log_y = -0.5 * float(phi @ phi) / prior_var + math.log(uniforms(0))
+
+    def inside(t):
+        x = phi + t * u
+        if not -0.5 * float(x @ x) / prior_var > log_y:
+            return False, None
+        s = float(action(x[None, :], L, m2, lam)[0])
+        return s < S_star, s
+
+    w = SLICE_WIDTH
+    lo = -w * uniforms(1)
+    hi = lo + w
+    J = int(math.floor(SLICE_MAX_STEPS * uniforms(2)))
+    K = SLICE_MAX_STEPS - 1 - J
+    while J > 0 and inside(lo)[0]:
+        lo -= w
+        J -= 1
+    while K > 0 and inside(hi)[0]:
+        hi += w
+        K -= 1
+    for i in range(SLICE_MAX_SHRINK):
+        t = lo + uniforms(3 + i) * (hi - lo)
+        ok, s = inside(t)
+        if ok:
+            return phi + t * u, s
+        if t < 0.0:
+            lo = t
+        else:
+            hi = t
+    return phi, S_cur
+
+
 def ns_run(L, m2, lam, n_live, k_delete, n_steps, prior_var=4.0, term_frac=1e-3,
            seed=0, run=0, eps0=None, acc_target=0.3, precision="fp64",
-           max_iter=1000000):
-    """Nested sampling run; returns log Z, its error bar, <|M|> and counters."""
+           max_iter=1000000, refill="rw"):
+    """Nested sampling run; returns log Z, its error bar, <|M|> and counters.
+
+    refill "rw": likelihood-constrained random walk (eps adapted per
+    iteration); "slice": n_steps slice moves per refilled point along
+    directions L z, L the factor of the survivors' covariance (no eps)."""
     d = L * L
     n, k = n_live, k_delete
     if not 0 < k < n:
@@ -126,6 +185,20 @@ def ns_run(L, m2, lam, n_live, k_delete, n_steps, prior_var=4.0, term_frac=1e-3,
         phi[dead] = phi[src]
         S[dead] = S[src]
         chol, _ = cholesky_jitter(covariance(phi[surv]))
+        if refill == "slice":
+            n_moved = 0
+            for s in range(n_steps):
+                U = rng.normals(seed, run, it, s, rng.PROPOSE, dead, d) @ chol.T
+                for j, row in enumerate(dead):
+                    def uniforms(q, row=row, s=s):
+                        return rng.slice_uniform(seed, run, it, s, int(row), q)
+                    new, s_new = slice_move(phi[row], U[j], S[row], S_star, prior_var, L,
+                                            m2, lam, uniforms)
+                    n_moved += int(not np.array_equal(new, phi[row]))
+                    phi[row] = new
+                    S[row] = s_new
+            accs.append(n_moved / (k * n_steps) if n_steps else 0.0)
+            continue
         B = eps * chol
         n_acc = 0
         for s in range(n_steps):

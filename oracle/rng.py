@@ -21,7 +21,9 @@ Stream map (shared convention of the oracle and the GPU path):
 
 * key = (seed, run), both 32-bit;
 * counter = (c0, c1, c2, c3) = (group, particle, step, level << 8 | purpose);
-* purposes: INIT = 1, PROPOSE = 2, ACCEPT = 3, RESAMPLE = 4, NS_PICK = 5;
+* purposes: INIT = 1, PROPOSE = 2, ACCEPT = 3, RESAMPLE = 4, NS_PICK = 5,
+  SLICE = 6 (the j-th uniform of a slice move is word j mod 4 of the call
+  with group j // 4);
 * normals for the d sites of a particle: site x takes word (x mod 4) of the
   call with group = x // 4; Box-Muller pairs words (0, 1) and (2, 3);
 * uniform from a word w: u = ((w >> 9) + 1/2) * 2^-23, i.e. the odd
@@ -46,6 +48,7 @@ PROPOSE = 2
 ACCEPT = 3
 RESAMPLE = 4
 NS_PICK = 5
+SLICE = 6
 
 _MASK32 = np.uint64(0xFFFFFFFF)
 _SHIFT32 = np.uint64(32)
@@ -120,6 +123,13 @@ def words(seed, run, level, step, purpose, particles):
 def accept_uniforms(seed, run, level, step, particles):
     """Metropolis uniforms u_i (float64) for one step."""
     return uniform(words(seed, run, level, step, ACCEPT, particles))
+
+
+def slice_uniform(seed, run, level, step, particle, j):
+    """The j-th uniform of a slice-sampling move (float64): word j mod 4 of
+    the call (group j // 4, particle, step, level/SLICE)."""
+    w = philox4x32_10(j // 4, particle, step, counter3(level, SLICE), seed, run)[j % 4]
+    return float(uniform(w))
 
 
 def resample_word(seed, run, level):
