@@ -54,7 +54,8 @@ enum {
 enum { PHI4_FP32 = 0, PHI4_BF16 = 1, PHI4_FP16 = 2 };
 
 /* Philox stream purposes (low byte of counter word 3). */
-enum { PHI4_INIT = 1, PHI4_PROPOSE = 2, PHI4_ACCEPT = 3, PHI4_RESAMPLE = 4, PHI4_NS_PICK = 5 };
+enum { PHI4_INIT = 1, PHI4_PROPOSE = 2, PHI4_ACCEPT = 3, PHI4_RESAMPLE = 4, PHI4_NS_PICK = 5,
+       PHI4_SLICE = 6 };
 
 /* Largest lattice, d = L*L sites: the register-resident fused sweep covers
  * d <= 256, the three-pass sweep the rest. */
@@ -116,7 +117,21 @@ typedef struct phi4_ns_config {
   uint32_t seed;
   uint32_t run;
   int32_t precision;
+  int32_t kernel;       /* refill: PHI4_NS_RW (0) or PHI4_NS_SLICE (1) */
 } phi4_ns_config;
+
+/* Refill kernels of nested sampling.
+ * PHI4_NS_RW: n_steps likelihood-constrained random-walk Metropolis steps,
+ *   phi' = phi + eps L z, eps steered to acc_target.
+ * PHI4_NS_SLICE: n_steps hit-and-run slice moves (the paper's NS kernel,
+ *   Sec. 2 (iv); App. A) of the prior restricted to S < S*, along directions
+ *   L z (L the factor of the survivors' covariance, z from the PROPOSE
+ *   stream), Neal's stepping-out (w = 1, at most 31 expansions) and
+ *   shrinkage (at most 64 draws, else the point stays); uniforms from the
+ *   SLICE stream, the j-th being word j mod 4 of the call (j / 4, row,
+ *   step, iteration << 8 | PHI4_SLICE).  float32 only; eps0 and acc_target
+ *   are unused, the acceptance reported is the fraction of moves. */
+enum { PHI4_NS_RW = 0, PHI4_NS_SLICE = 1 };
 
 /* ------------------------------------------------------------------ SMC */
 
@@ -357,6 +372,19 @@ int phi4_mutate(const float* src, float* dst, const int32_t* rows, int32_t n, in
                 int32_t step0, int32_t n_steps, float zsign, int32_t precision, float* S,
                 float* absM, unsigned long long* acc_count, uint8_t* acc_flags, float* prop,
                 void* workspace, size_t workspace_bytes, void* stream);
+
+/* One slice move of each row phi[rows[i]] (rows NULL: i), i < n, along the
+ * direction dirs[i*d ..] (float32, caller-given): the move the slice refill
+ * of nested sampling makes (PHI4_NS_SLICE: prior N(0, prior_var I)
+ * restricted to S < s_star, Neal's stepping-out and shrinkage, uniforms of
+ * the SLICE stream at (level, step) with the row as particle).  S[row]
+ * must hold the row's action on entry; rows that move get their new field,
+ * S and (absM optional) |M|.  Rows must be distinct.  Asynchronous on
+ * stream; no workspace. */
+int phi4_slice_move(float* phi, const int32_t* rows, const float* dirs, int32_t n, int32_t L,
+                    double m2, double lambda, double s_star, double prior_var, uint32_t seed,
+                    uint32_t run, int32_t level, int32_t step, float* S, float* absM,
+                    void* stream);
 
 #ifdef __cplusplus
 }

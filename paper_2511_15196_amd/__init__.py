@@ -16,7 +16,8 @@ from ._abi import (  # noqa: F401
     PHI4_OK, PHI4_DONE, PHI4_EINVAL, PHI4_EHIP, PHI4_ECHOL, PHI4_ENONFINITE,
     PHI4_FP32, PHI4_BF16, PHI4_FP16, PHI4_INIT, PHI4_PROPOSE, PHI4_ACCEPT,
     PHI4_RESAMPLE, PHI4_NS_PICK, PHI4_MAX_SITES, PHI4_KERNEL_RW, PHI4_KERNEL_IRMH, PHI4_KERNEL_HMC,
-    PHI4_IRMH_MAX_SITES, KERNELS, Phi4Error, SmcConfig, NsConfig, lib, library_path,
+    PHI4_IRMH_MAX_SITES, KERNELS, PHI4_NS_RW, PHI4_NS_SLICE, PHI4_SLICE, NS_KERNELS, Phi4Error,
+    SmcConfig, NsConfig, lib, library_path,
 )
 
 PRECISIONS = {"fp32": PHI4_FP32, "bf16": PHI4_BF16, "fp16": PHI4_FP16}
@@ -230,6 +231,17 @@ def phi4_whiten(phi, N, d, L, r, workspace, rows=None, mu=None, stream=None):
                              _stream(stream)), "phi4_whiten")
 
 
+def phi4_slice_move(phi, n, L, m2, lam, s_star, prior_var, seed, run, level, step, dirs, S,
+                    rows=None, absM=None, stream=None):
+    _require_cuda(phi, dirs, S, rows, absM)
+    _check(lib().phi4_slice_move(_ptr(phi), _ptr(rows), _ptr(dirs), ctypes.c_int32(n),
+                                 ctypes.c_int32(L), ctypes.c_double(m2), ctypes.c_double(lam),
+                                 ctypes.c_double(s_star), ctypes.c_double(prior_var),
+                                 ctypes.c_uint32(seed), ctypes.c_uint32(run), ctypes.c_int32(level),
+                                 ctypes.c_int32(step), _ptr(S), _ptr(absM), _stream(stream)),
+           "phi4_slice_move")
+
+
 def phi4_cholesky(sigma, d, L, workspace, stream=None):
     _require_cuda(sigma, L, workspace)
     tau = ctypes.c_double()
@@ -314,12 +326,12 @@ class NS:
 
     def __init__(self, L, n_live, k_delete, n_steps, m2, lam, prior_var=4.0, term_frac=1e-3,
                  acc_target=0.3, eps0=0.0, seed=0, run=0, precision="fp32", sweep="auto",
-                 device="cuda"):
+                 device="cuda", kernel="rw"):
         import torch
         self.cfg = NsConfig(L=L, n_live=n_live, k_delete=k_delete, n_steps=n_steps, m2=m2,
                             lambda_=lam, prior_var=prior_var, term_frac=term_frac,
                             acc_target=acc_target, eps0=eps0, seed=seed, run=run,
-                            precision=PRECISIONS[precision])
+                            precision=PRECISIONS[precision], kernel=NS_KERNELS[kernel])
         nbytes = ns_workspace_bytes(self.cfg)
         if nbytes == 0:
             raise Phi4Error(PHI4_EINVAL, "invalid nested-sampling configuration")

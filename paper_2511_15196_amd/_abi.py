@@ -11,6 +11,9 @@ PHI4_MAX_SITES = 4096
 PHI4_KERNEL_RW, PHI4_KERNEL_IRMH, PHI4_KERNEL_HMC = 0, 1, 2
 PHI4_IRMH_MAX_SITES = 1024
 KERNELS = {"rw": PHI4_KERNEL_RW, "irmh": PHI4_KERNEL_IRMH, "hmc": PHI4_KERNEL_HMC}
+PHI4_NS_RW, PHI4_NS_SLICE = 0, 1
+NS_KERNELS = {"rw": PHI4_NS_RW, "slice": PHI4_NS_SLICE}
+PHI4_SLICE = 6
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libphi4pmc.so")
@@ -55,6 +58,7 @@ class NsConfig(ctypes.Structure):
         ("seed", ctypes.c_uint32),
         ("run", ctypes.c_uint32),
         ("precision", ctypes.c_int32),
+        ("kernel", ctypes.c_int32),
     ]
 
 
@@ -95,6 +99,8 @@ SIGNATURES = {
     "phi4_reweight": (ctypes.c_int, [_V, _I32, _D, _D, _V, _PD, _V, _SZ, _V]),
     "phi4_covariance": (ctypes.c_int, [_V, _V, _I32, _I32, _V, _V, _SZ, _V]),
     "phi4_whiten_workspace_bytes": (ctypes.c_size_t, [_I32, _I32]),
+    "phi4_slice_move": (ctypes.c_int, [_V, _V, _V, _I32, _I32, _D, _D, _D, _D, _U32, _U32, _I32,
+                                       _I32, _V, _V, _V]),
     "phi4_whiten": (ctypes.c_int, [_V, _V, _I32, _I32, _V, _V, _V, _V, _SZ, _V]),
     "phi4_cholesky": (ctypes.c_int, [_V, _I32, _V, _PD, _V, _SZ, _V]),
     "phi4_step_workspace_bytes": (_SZ, [_I32, _I32]),

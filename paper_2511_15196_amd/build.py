@@ -19,7 +19,7 @@ OUT_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libphi4pmc.so")
 
 SOURCES = ["k_field.hip", "k_mutate.hip", "k_large.hip", "k_irmh.hip", "k_hmc.hip", "k_reweight.hip",
-           "k_factor.hip", "k_ns.hip", "abi.cpp"]
+           "k_slice.hip", "k_factor.hip", "k_ns.hip", "abi.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950",

@@ -15,6 +15,7 @@
 #include "common.hpp"
 #include "hmc.hpp"
 #include "irmh.hpp"
+#include "slice.hpp"
 
 using namespace phi4;
 
@@ -199,6 +200,8 @@ struct Handle {
   LargeScratch nlarge;
   int32_t* nbstatus;
   double* nbscr;
+  double* sone;      // slice refill: 1.0 (unit scale of the emitted factor)
+  float* szero;      // slice refill: d zeros (base row of the direction product)
   // host mirrors
   void* pinned;      // two state copies
   void* pinned_dev;  // the same memory as the device addresses it
@@ -415,8 +418,16 @@ size_t ns_carve(const phi4_ns_config& c, void* ws, Handle* h) {
   const LargeScratch large = take_large(cv, k, d);
   int32_t* bstatus = cv.take<int32_t>(kJitterAttempts + 1);
   double* bscr = cv.take<double>(blocked_scratch_doubles(d));
+  double* one = nullptr;
+  float* zero = nullptr;
+  if (c.kernel == PHI4_NS_SLICE) {
+    one = cv.take<double>(1);
+    zero = cv.take<float>(d);
+  }
   if (h) {
     h->nlarge = large;
+    h->sone = one;
+    h->szero = zero;
     h->nbstatus = bstatus;
     h->nbscr = bscr;
     h->nst = st;
@@ -444,6 +455,9 @@ bool ns_valid(const phi4_ns_config* c, std::string* why) {
   if (!(c->term_frac > 0.0 && c->term_frac < 1.0)) return *why = "term_frac must be in (0, 1)", false;
   if (!std::isfinite(c->m2) || !std::isfinite(c->lambda)) return *why = "couplings must be finite", false;
   if (!mutate_supported((int)d, c->precision)) return *why = "unsupported precision", false;
+  if (c->kernel != PHI4_NS_RW && c->kernel != PHI4_NS_SLICE) return *why = "unknown refill kernel", false;
+  if (c->kernel == PHI4_NS_SLICE && c->precision != PHI4_FP32)
+    return *why = "the slice refill runs in float32 only", false;
   return true;
 }
 
@@ -862,6 +876,7 @@ int ns_init(const phi4_ns_config* cfg, float* phi, float* S, void* workspace,
   ns_carve(*cfg, workspace, h);
   launch_cov_init(h->part, h->nplan, h->stream);
   launch_large_init(h->nlarge, cfg->k_delete, h->stream);
+  if (cfg->kernel == PHI4_NS_SLICE) launch_slice_init(h->szero, h->d, h->sone, h->stream);
   int rc = alloc_pinned(h, sizeof(NsState));
   if (rc) {
     delete h;
@@ -893,7 +908,8 @@ int ns_step(void* handle, int32_t* done_host) {
   fa.A = h->A;
   fa.Bt = h->Bt;
   fa.ldb = h->d;
-  fa.eps_ptr = &h->nst->eps;
+  // the slice refill draws its directions from L itself
+  fa.eps_ptr = h->ns.kernel == PHI4_NS_SLICE ? h->sone : &h->nst->eps;
   fa.tau_out = &h->nst->tau;
   fa.err_out = &h->nst->err;
   fa.done = &h->nst->done;
@@ -929,7 +945,8 @@ int ns_step(void* handle, int32_t* done_host) {
   int rc;
   {
     TimedLaunch tl(h);
-    rc = launch_mutate(m, h->precision, h->stream);
+    rc = h->ns.kernel == PHI4_NS_SLICE ? launch_slice_sweep(m, h->szero, h->stream)
+                                       : launch_mutate(m, h->precision, h->stream);
   }
   if (rc) return fail(rc, "ns_step: unsupported shape");
   rc = hip_check("ns_step");
@@ -1144,6 +1161,34 @@ int phi4_reweight(const float* S, int32_t N, double beta, double ess_frac, doubl
   HIP_TRY(hipStreamSynchronize(s));
   if (!std::isfinite(out_host[0])) return fail(PHI4_ENONFINITE, "phi4_reweight: non-finite actions or stalled solve");
   return PHI4_OK;
+}
+
+int phi4_slice_move(float* phi, const int32_t* rows, const float* dirs, int32_t n, int32_t L,
+                    double m2, double lambda, double s_star, double prior_var, uint32_t seed,
+                    uint32_t run, int32_t level, int32_t step, float* S, float* absM,
+                    void* stream) {
+  const long long d = (long long)L * L;
+  if (n < 0 || L < 1 || d > PHI4_MAX_SITES || !phi || !dirs || !S || !(prior_var > 0.0))
+    return fail(PHI4_EINVAL, "phi4_slice_move: need phi, dirs, S, 1 <= L*L <= 4096, prior_var > 0");
+  SliceArgs sa = {};
+  sa.phi = phi;
+  sa.rows = rows;
+  sa.dirs = dirs;
+  sa.n = n;
+  sa.L = L;
+  sa.d = (int)d;
+  sa.m2 = (float)m2;
+  sa.lam = (float)lambda;
+  sa.s_star = (float)s_star;
+  sa.inv_prior_var = (float)(1.0 / prior_var);
+  sa.seed = seed;
+  sa.run = run;
+  sa.level = level;
+  sa.step = (uint32_t)step;
+  sa.S = S;
+  sa.absM = absM;
+  launch_slice_moves(sa, static_cast<hipStream_t>(stream));
+  return hip_check("phi4_slice_move");
 }
 
 size_t phi4_whiten_workspace_bytes(int32_t N, int32_t d) {

@@ -29,6 +29,7 @@
 
 #include "common.hpp"
 #include "irmh.hpp"
+#include "slice.hpp"
 
 namespace phi4 {
 
@@ -995,6 +996,49 @@ int launch_irmh_sweep(const MutateArgs& a, const double* A, const IrmhScratch& q
     const hipError_t e = hipMemcpyAsync(a.prop, w.prop, sizeof(float) * (size_t)n * d,
                                         hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return PHI4_EHIP;
+  }
+  acc_sum_kernel<<<1, 1024, 0, s>>>(w.accp, n, a.n_steps, a.acc_count, a.prop_count, a.done_ptr);
+  return PHI4_OK;
+}
+
+// n_steps slice moves of the rows a.rows of a.dst (a.Bt = L^T unscaled):
+// per step the normals of the PROPOSE stream, the directions z L^T on the
+// proposal-product kernel with a zero base row, then one slice move per
+// point; moves are counted per slot and summed once at the end.
+int launch_slice_sweep(const MutateArgs& a, const float* zero, hipStream_t s) {
+  if (a.n <= 0 || a.n_steps <= 0) return PHI4_OK;
+  const int n = a.n, d = a.d, dz = large_dz(d);
+  const LargeScratch& w = a.large;
+  const int tile = gemm_tile(w, n, d, PHI4_FP32, s);
+  const dim3 g((unsigned)(dz / 32), (unsigned)(dz / 32));
+  lp_kernel<PHI4_FP32><<<g, 256, 0, s>>>(a.Bt, a.ldb, d, dz, w.lp, a.done_ptr);
+  const long long nz = (long long)n * (dz / 4);
+  for (int t = 0; t < a.n_steps; ++t) {
+    const uint32_t step = (uint32_t)(a.step0 + t);
+    z_kernel<PHI4_FP32><<<(unsigned)((nz + 255) / 256), 256, 0, s>>>(
+        w.z, n, d, dz, a.rows, step, a.level, a.level_ptr, a.seed, a.run, 1.0f, w.zsgn,
+        a.done_ptr);
+    launch_gemm<PHI4_FP32>(tile, w, zero, nullptr, n, d, a.done_ptr, s, 0);
+    SliceArgs sa = {};
+    sa.phi = a.dst;
+    sa.rows = a.rows;
+    sa.dirs = w.prop;
+    sa.n = n;
+    sa.L = a.L;
+    sa.d = d;
+    sa.m2 = a.m2;
+    sa.lam = a.lam;
+    sa.sstar_ptr = a.sstar_ptr;
+    sa.inv_prior_var = a.inv_prior_var;
+    sa.seed = a.seed;
+    sa.run = a.run;
+    sa.level_ptr = a.level_ptr;
+    sa.step = step;
+    sa.done = a.done_ptr;
+    sa.S = a.S;
+    sa.absM = a.absM;
+    sa.accp = w.accp;
+    launch_slice_moves(sa, s);
   }
   acc_sum_kernel<<<1, 1024, 0, s>>>(w.accp, n, a.n_steps, a.acc_count, a.prop_count, a.done_ptr);
   return PHI4_OK;
