@@ -157,10 +157,10 @@ def smc_workload(P, torch, L, N, m2, lam, n_steps, precision, seed=0, kernel="rw
     return out
 
 
-def ns_workload(P, torch, L, n, k, n_steps, precision, iters, warm=2, seed=0):
+def ns_workload(P, torch, L, n, k, n_steps, precision, iters, warm=2, seed=0, kernel="rw"):
     """`iters` timed nested-sampling iterations after `warm` untimed ones."""
     ns = P.NS(L, n, k, n_steps, -4.0, 8.0, prior_var=4.0, term_frac=1e-3, seed=seed,
-              precision=precision)
+              precision=precision, kernel=kernel)
     for _ in range(warm):
         P.ns_step(ns.h, sync=False)
     P.phi4_kernel_time(ns.h)
@@ -298,6 +298,12 @@ def extra_workloads(P, torch, match=""):
         if want(name):
             ex[name] = ns_workload(P, torch, 32, 4096, 2048, 40, prec, 8)
             progress(f"NS L=32 {prec} done")
+    for L in (16, 32):
+        name = f"ns_slice_L{L}_n4096_k2048_fp32"
+        if want(name):
+            # one particle-update = one slice move of one refilled point
+            ex[name] = ns_workload(P, torch, L, 4096, 2048, 5, "fp32", 8, kernel="slice")
+            progress(f"NS slice L={L} done")
     if want("paper_point_smc_rw"):
         ex["paper_point_smc_rw"] = paper_point(P, torch)
     return ex
