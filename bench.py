@@ -309,6 +309,27 @@ def extra_workloads(P, torch, match=""):
     return ex
 
 
+def product_tiles(P, torch, L=64, N=8192, steps=5):
+    """The proposal product at one large shape with every tile pinned in turn:
+    a 5-step sweep (normals, product, accept per step) after one level, per
+    precision and tile, timed with HIP events (profiling aid)."""
+    d = L * L
+    out = {}
+    for prec in ("bf16", "fp32"):
+        for tile in [(32, 64, 256), (64, 64, 256), (128, 64, 256), (128, 128, 256), (128, 128, 512)]:
+            P.phi4_set_tile(N, d, prec, *tile)
+            s = P.SMC(L, N, -4.0, 8.0, ess_frac=0.5, n_steps=steps, seed=0, precision=prec)
+            P.smc_reweight_resample(s.h)
+            torch.cuda.synchronize()
+            P.phi4_set_timing(s.h, True)
+            P.smc_mutate(s.h)
+            torch.cuda.synchronize()
+            ms, _ = P.phi4_kernel_time(s.h)
+            out[f"{prec}_{tile[0]}x{tile[1]}x{tile[2]}"] = dict(sweep_ms=ms, steps=steps)
+            s.close()
+    return out
+
+
 def copy_probe(torch, mib):
     n = int(mib * (1 << 20)) // 4
     x = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -338,6 +359,8 @@ def main():
         return
     if args.only_extra:
         ex = extra_workloads(P, torch, args.extra_match)
+        if args.extra_match and args.extra_match in "product_tiles_L64_N8192":
+            ex["product_tiles_L64_N8192"] = product_tiles(P, torch)
         if args.batch_levels > 0 and args.extra_match in "batch64":
             ex["batch64"] = batch_workload(P, torch, args.batch_levels)
         print(json.dumps({"workloads": ex}), flush=True)

@@ -9,8 +9,8 @@
 //      pass of the step before for the others (its ALUs are idle while its
 //      row loads are in flight);
 //   2. proposal: phi'[p][c] = phi[p][c] + sum_{k <= c} z[p][k] Bt[k][c] on the
-//      matrix cores, 64 x 64 output tiles staged through LDS, only the
-//      K range on or above the diagonal of the triangular factor; the
+//      matrix cores, output tiles staged through LDS (XCD-aware tile order),
+//      only the K range on or above the diagonal of the triangular factor; the
 //      16-bit forms take s M(s z) with s the sign of the row's first
 //      normal, so that the increment is odd in z (exactly symmetric
 //      proposal, no Hastings term) at the cost of one product;
@@ -170,9 +170,17 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const void* __restrict__ zin,
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int pl = lane & 15, gl = lane >> 4;
   const int wr = wv / WC, wc = wv % WC;
-  const int p0 = blockIdx.y * BM;
+  // XCD-aware order: workgroups go round-robin to the 8 XCDs, so the
+  // dispatch index i is remapped to the tile (i mod 8) G/8 + i div 8: each
+  // XCD takes a contiguous run of tiles (column pairs of one particle tile,
+  // then the next), and the workgroups resident on one XCD share their z
+  // rows and factor columns in that XCD's L2
+  const int G = gridDim.x * gridDim.y;
+  const int lin = blockIdx.y * gridDim.x + blockIdx.x;
+  const int tile = (G & 7) ? lin : (lin & 7) * (G >> 3) + (lin >> 3);
+  const int p0 = (tile / gridDim.x) * BM;
   const int J = (d + BN - 1) / BN;
-  const int x = blockIdx.x;
+  const int x = tile % gridDim.x;
   const int ntile = (J - 1 - x > x) ? 2 : 1;
   const T* z = static_cast<const T*>(zin);
   const T* lp = static_cast<const T*>(lpin);
