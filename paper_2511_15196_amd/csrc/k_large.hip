@@ -395,7 +395,9 @@ struct AcceptArgs {
   float* zz_out;
 };
 
-template <bool CONSTRAINED, int PER, bool IND = false>   // PER >= d / kAT sites per thread
+// VEC (d a multiple of 4, PER >= 4): each thread loads its sites as float4
+// quads of consecutive sites (quad tid + kAT j) instead of single floats.
+template <bool CONSTRAINED, int PER, bool IND = false, bool VEC = false>   // PER >= d / kAT
 __global__ __launch_bounds__(kAT) void accept_kernel(AcceptArgs a) {
   constexpr int NV = IND ? 7 : 6;   // reduced sums
   extern __shared__ __align__(16) float rowbuf[];   // d pairs (phi, phi')
@@ -412,11 +414,30 @@ __global__ __launch_bounds__(kAT) void accept_kernel(AcceptArgs a) {
     const float* cp = a.cur + (size_t)cr * d;
     const float* pp = a.prop + (size_t)p * d;
     float vo[PER], vn[PER];
+    if constexpr (VEC) {
+      static_assert(PER % 4 == 0, "quads of sites");
+      const int nq4 = d / 4;
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int x = min(tid + i * kAT, d - 1);
-      vo[i] = cp[x];
-      vn[i] = pp[x];
+      for (int j = 0; j < PER / 4; ++j) {
+        const int q = min(tid + j * kAT, nq4 - 1);
+        const float4 o = reinterpret_cast<const float4*>(cp)[q];
+        const float4 w = reinterpret_cast<const float4*>(pp)[q];
+        vo[4 * j] = o.x;
+        vo[4 * j + 1] = o.y;
+        vo[4 * j + 2] = o.z;
+        vo[4 * j + 3] = o.w;
+        vn[4 * j] = w.x;
+        vn[4 * j + 1] = w.y;
+        vn[4 * j + 2] = w.z;
+        vn[4 * j + 3] = w.w;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int x = min(tid + i * kAT, d - 1);
+        vo[i] = cp[x];
+        vn[i] = pp[x];
+      }
     }
     if (a.znext && !(a.done && *a.done)) {
       const uint32_t c3p =
@@ -446,9 +467,21 @@ __global__ __launch_bounds__(kAT) void accept_kernel(AcceptArgs a) {
         }
       }
     }
+    if constexpr (VEC) {
 #pragma unroll
-    for (int i = 0; i < PER; ++i)
-      if (tid + i * kAT < d) f[tid + i * kAT] = make_float2(vo[i], vn[i]);
+      for (int j = 0; j < PER / 4; ++j) {
+        const int q = tid + j * kAT;
+        if (q < d / 4) {
+          float4* f4 = reinterpret_cast<float4*>(f + 4 * q);
+          f4[0] = make_float4(vo[4 * j], vn[4 * j], vo[4 * j + 1], vn[4 * j + 1]);
+          f4[1] = make_float4(vo[4 * j + 2], vn[4 * j + 2], vo[4 * j + 3], vn[4 * j + 3]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < PER; ++i)
+        if (tid + i * kAT < d) f[tid + i * kAT] = make_float2(vo[i], vn[i]);
+    }
   }
   __syncthreads();
   // S(phi), S(phi'), sum of per-site differences, dU0, M(phi), M(phi');
@@ -727,14 +760,18 @@ void launch_accept(int per, int n, size_t lds, const AcceptArgs& aa, hipStream_t
       accept_wave_kernel<CONSTRAINED, 4, IND><<<g, 64 * kAW, wl, st>>>(aa);
     return;
   }
+  const bool vec = aa.d % 4 == 0;   // rows 16-byte aligned: quad loads
   if (per <= 2)
     accept_kernel<CONSTRAINED, 2, IND><<<n, kAT, lds, st>>>(aa);
   else if (per <= 4)
-    accept_kernel<CONSTRAINED, 4, IND><<<n, kAT, lds, st>>>(aa);
+    vec ? accept_kernel<CONSTRAINED, 4, IND, true><<<n, kAT, lds, st>>>(aa)
+        : accept_kernel<CONSTRAINED, 4, IND><<<n, kAT, lds, st>>>(aa);
   else if (per <= 8)
-    accept_kernel<CONSTRAINED, 8, IND><<<n, kAT, lds, st>>>(aa);
+    vec ? accept_kernel<CONSTRAINED, 8, IND, true><<<n, kAT, lds, st>>>(aa)
+        : accept_kernel<CONSTRAINED, 8, IND><<<n, kAT, lds, st>>>(aa);
   else
-    accept_kernel<CONSTRAINED, 16, IND><<<n, kAT, lds, st>>>(aa);
+    vec ? accept_kernel<CONSTRAINED, 16, IND, true><<<n, kAT, lds, st>>>(aa)
+        : accept_kernel<CONSTRAINED, 16, IND><<<n, kAT, lds, st>>>(aa);
 }
 
 // One step.  With q (independence sampler, float32): the proposal is
