@@ -40,8 +40,8 @@ VALU_PEAK = 256 * 4 * 16 * 2.4e9
 # counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0: the factors that make a
 # 256 MiB device-to-device copy read and write 256 MiB on the same counters),
 # valid only for the kernel sources they were taken on.
-TRAFFIC = dict(bytes_per_launch=(516.40 * 1.99980 + 1072.0) * 1024,
-               sources={"k_mutate.hip": "9d73ba65343919455708a3e7da700cc69f132734f4ba260e38d111557c397d9c",
+TRAFFIC = dict(bytes_per_launch=(522.67 * 1.99980 + 1072.0) * 1024,
+               sources={"k_mutate.hip": "26605c7513a29824394111bc1e341cf29d04727df616bd695ece70439d7efb90",
                         "common.hpp": "4097ce027518c90000269a1063c71e114baf0749c9547a9753dffa4777d92be5"})
 
 

@@ -10,12 +10,17 @@
 //   Metropolis test with u from the ACCEPT stream.
 //
 // Work split: the tile is 16 particles x DP sites (DP = d rounded up to a
-// multiple of 16).  The W waves of the workgroup generate the 16 x DP
-// normals together into LDS; wave w owns the 16-column blocks nb with
-// nb % 2W in {w, 2W-1-w} (a snake that balances the triangular MFMA work),
-// keeps its B fragments in registers for the whole sweep and holds the
-// fields of its columns in the MFMA output layout (lane (p, g) holds rows
-// 4g..4g+3 of column 16 nb + p).  dS is accumulated from per-site
+// multiple of 16), on W x H waves.  The waves generate the 16 x DP normals
+// together into LDS; column-block set c (of W) holds the 16-column blocks nb
+// with nb % 2W in {c, 2W-1-c} (a snake that balances the triangular MFMA
+// work).  Each of the set's H waves keeps the set's B fragments in
+// registers for the whole sweep and forms the set's whole product, whose
+// MFMA output layout gives lane (p, g) rows 4g..4g+3 of column 16 nb + p;
+// of these the wave owns 4 / H rows, whose fields it holds and whose
+// stencil and Metropolis terms it evaluates.  With H = 2 at d <= 128 a tile
+// of 16 particles runs 8 waves instead of 4, so that at N = 4096 every SIMD
+// holds two waves to hide each other's latency (the per-site sums and every
+// result are unchanged, bit for bit).  dS is accumulated from per-site
 // differences so that float32 does not cancel |S|.
 //
 // Pipelining: the normals do not depend on the fields, so the tile's
@@ -69,10 +74,13 @@ __device__ __forceinline__ float row16_sum(float v) {
   return v;
 }
 
-template <int DP_, int W_, int PREC_, int KIND_>
+template <int DP_, int W_, int PREC_, int KIND_, int H_ = 1>
 struct Cfg {
   static constexpr int DP = DP_;
   static constexpr int W = W_;
+  static constexpr int H = H_;          // waves per column block (row split)
+  static constexpr int JJ = 4 / H_;     // tile rows per lane
+  static constexpr int NT = 64 * W_ * H_;
   static constexpr int PREC = PREC_;
   static constexpr bool CONSTRAINED = KIND_ == 1;   // likelihood-constrained (else tempered)
   static constexpr bool F32 = PREC_ == PHI4_FP32;
@@ -93,8 +101,9 @@ struct Cfg {
 };
 
 template <class C>
-__global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
+__global__ __launch_bounds__(C::NT) void mutate_kernel(MutateArgs a) {
   constexpr int W = C::W, NBW = C::NBW, ZS = C::ZS, XS = C::XS, DPZ = C::DPZ;
+  constexpr int JJ = C::JJ, NT = C::NT;
   constexpr bool F32 = C::F32;
   using ZT = typename std::conditional<F32, float, unsigned short>::type;
   using FragT = typename std::conditional<F32, f32x4, u16x8>::type;
@@ -112,6 +121,14 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int p = lane & 15, g = lane >> 4;
+  // wave wv works on column-block set cw and, of each lane's four MFMA
+  // output rows 4g .. 4g+3, on rows 4g + jb .. 4g + jb + JJ - 1.  Both waves
+  // of a set form its whole product (the triangular MFMA work grows with
+  // the block index); the second half of the waves takes the sets in reverse
+  // order, so that waves wv and wv + W, which share a SIMD when the waves of
+  // a workgroup are placed round-robin, carry equal MFMA work together.
+  const int hh = C::H == 1 ? 0 : wv / W;
+  const int cw = (hh & 1) ? W - 1 - wv % W : wv % W, jb = hh * JJ;
   const int base = blockIdx.x * 16;
   const int n = a.n, d = a.d, L = a.L;
 
@@ -125,11 +142,11 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
 
   // rows of this lane's output particles (tile slots 4g + jj) and of the
   // fields they start from
-  int orow[4], irow[4];
-  bool oval[4];
+  int orow[JJ], irow[JJ];
+  bool oval[JJ];
 #pragma unroll
-  for (int jj = 0; jj < 4; ++jj) {
-    const int i = base + 4 * g + jj;
+  for (int jj = 0; jj < JJ; ++jj) {
+    const int i = base + 4 * g + jb + jj;
     oval[jj] = i < n;
     const int ic = min(i, n - 1);              // valid index, masked below
     const int r = a.rows ? a.rows[ic] : ic;
@@ -143,7 +160,7 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
   bool cval[NBW];
 #pragma unroll
   for (int j = 0; j < NBW; ++j) {
-    nbs[j] = j * W + ((j & 1) ? (W - 1 - wv) : wv);
+    nbs[j] = j * W + ((j & 1) ? (W - 1 - cw) : cw);
     const int x = 16 * nbs[j] + p;
     col[j] = x;
     cval[j] = x < d;
@@ -184,11 +201,11 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
   }
 
   // fields of the owned columns
-  float ph[NBW][4], pn[NBW][4];
+  float ph[NBW][JJ], pn[NBW][JJ];
 #pragma unroll
   for (int j = 0; j < NBW; ++j)
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj)
+    for (int jj = 0; jj < JJ; ++jj)
     {
       const float v = a.src[(size_t)irow[jj] * d + min(col[j], d - 1)];
       ph[j][jj] = (oval[jj] && cval[j]) ? v : 0.f;
@@ -196,21 +213,23 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
 
   // 16-bit K = 32 needs z columns DP..31 of a 16-column tile to be zero
   if constexpr (DPZ > C::DP) {
-    for (int e = tid; e < 2 * 16 * (DPZ - C::DP); e += 64 * W) {
+    for (int e = tid; e < 2 * 16 * (DPZ - C::DP); e += NT) {
       const int b = e / (16 * (DPZ - C::DP)), r = e % (16 * (DPZ - C::DP));
       zs[b][(r / (DPZ - C::DP)) * ZS + C::DP + r % (DPZ - C::DP)] = 0;
     }
   }
 
-  // physical rows of the Z-phase calls (fixed over the sweep)
-  int zrow[NBW];
-  bool zval[NBW];
+  // physical rows of the Z-phase calls (fixed over the sweep): 4 DP calls
+  // of four normals per step, ZC per thread
+  constexpr int NZC = 4 * C::DP, ZC = (NZC + NT - 1) / NT;
+  int zrow[ZC];
+  bool zval[ZC];
 #pragma unroll
-  for (int i = 0; i < NBW; ++i) {
-    const int c = tid + 64 * W * i;
+  for (int i = 0; i < ZC; ++i) {
+    const int c = tid + NT * i;
     const int ps = c & 15, q = c >> 4;
     const int ti = base + ps;
-    zval[i] = ti < n && 4 * q < d;
+    zval[i] = c < NZC && ti < n && 4 * q < d;
     const int tc = min(ti, n - 1);
     const int r = a.rows ? a.rows[tc] : tc;
     zrow[i] = zval[i] ? r : 0;
@@ -219,8 +238,9 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
   // normals of one step into zs[buf]: NBW Philox calls per lane
   auto draw_normals = [&](int buf, uint32_t step) {
 #pragma unroll
-    for (int i = 0; i < NBW; ++i) {
-      const int c = tid + 64 * W * i;
+    for (int i = 0; i < ZC; ++i) {
+      const int c = tid + NT * i;
+      if (NZC % NT != 0 && c >= NZC) break;   // whole waves
       const int ps = c & 15, q = c >> 4;
       float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
       if (zval[i]) {
@@ -246,7 +266,7 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
   // log-uniforms of the ACCEPT stream for steps s0 .. s0 + kAccChunk - 1
   auto draw_uniforms = [&](int s0) {
     const int lb = (s0 / kAccChunk) & 1;
-    for (int e = tid; e < 16 * kAccChunk; e += 64 * W) {
+    for (int e = tid; e < 16 * kAccChunk; e += NT) {
       const int sl = e & 15, ss = e >> 4;
       const int ti = base + sl;
       float lu = 0.f;
@@ -314,28 +334,51 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
     }
 
     // 16-bit forms: signs of the rows of this lane's outputs (rows 4g + jj)
-    bool oneg[4] = {false, false, false, false};
+    bool oneg[JJ];
+#pragma unroll
+    for (int jj = 0; jj < JJ; ++jj) oneg[jj] = false;
     if constexpr (!F32) {
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj)
-        oneg[jj] = reinterpret_cast<const unsigned short*>(&zs[cb][(4 * g + jj) * ZS])[0] & 0x8000u;
+      for (int jj = 0; jj < JJ; ++jj)
+        oneg[jj] =
+            reinterpret_cast<const unsigned short*>(&zs[cb][(4 * g + jb + jj) * ZS])[0] & 0x8000u;
     }
+    if constexpr (JJ == 4) {
 #pragma unroll
-    for (int j = 0; j < NBW; ++j)
+      for (int j = 0; j < NBW; ++j)
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const float inc = F32 ? (acc[j][jj] + accn[j][jj]) + (acc2[j][jj] + acc3[j][jj])
-                              : (oneg[jj] ? -acc[j][jj] : acc[j][jj]);
-        pn[j][jj] = ph[j][jj] + inc;
+        for (int jj = 0; jj < 4; ++jj) {
+          const float inc = F32 ? (acc[j][jj] + accn[j][jj]) + (acc2[j][jj] + acc3[j][jj])
+                                : (oneg[jj] ? -acc[j][jj] : acc[j][jj]);
+          pn[j][jj] = ph[j][jj] + inc;
+        }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NBW; ++j) {
+        float o[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          o[r] = F32 ? (acc[j][r] + accn[j][r]) + (acc2[j][r] + acc3[j][r]) : acc[j][r];
+#pragma unroll
+        for (int jj = 0; jj < JJ; ++jj) {
+          // output row jb + jj of the lane (jb is wave-uniform: selects, no
+          // indexed register access)
+          float v = o[0];
+#pragma unroll
+          for (int r = 1; r < 4; ++r)
+            if (r == jb + jj) v = o[r];
+          pn[j][jj] = ph[j][jj] + (F32 ? v : (oneg[jj] ? -v : v));
+        }
       }
+    }
 
     // ---- exchange old and new fields for the stencil
 #pragma unroll
     for (int j = 0; j < NBW; ++j)
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        xo[(4 * g + jj) * XS + col[j]] = ph[j][jj];
-        xn[(4 * g + jj) * XS + col[j]] = pn[j][jj];
+      for (int jj = 0; jj < JJ; ++jj) {
+        xo[(4 * g + jb + jj) * XS + col[j]] = ph[j][jj];
+        xn[(4 * g + jb + jj) * XS + col[j]] = pn[j][jj];
       }
 
     __syncthreads();
@@ -343,14 +386,16 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
     // ---- per-site terms: tempered -> (dS, dU0); constrained -> (S', dU0).
     // Neighbour values of all owned sites are read first (one LDS round
     // trip); columns beyond d contribute zero.
-    float r0[4] = {0.f, 0.f, 0.f, 0.f}, r1[4] = {0.f, 0.f, 0.f, 0.f};
+    float r0[JJ], r1[JJ];
+#pragma unroll
+    for (int jj = 0; jj < JJ; ++jj) r0[jj] = r1[jj] = 0.f;
     {
-      float n1n[NBW][4], n0n[NBW][4], n1o[NBW][4], n0o[NBW][4];
+      float n1n[NBW][JJ], n0n[NBW][JJ], n1o[NBW][JJ], n0o[NBW][JJ];
 #pragma unroll
       for (int j = 0; j < NBW; ++j)
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          const int rb = (4 * g + jj) * XS;
+        for (int jj = 0; jj < JJ; ++jj) {
+          const int rb = (4 * g + jb + jj) * XS;
           n1n[j][jj] = xn[rb + y1[j]];
           n0n[j][jj] = xn[rb + y0[j]];
           if constexpr (!constrained) {
@@ -361,7 +406,7 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
 #pragma unroll
       for (int j = 0; j < NBW; ++j)
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
+        for (int jj = 0; jj < JJ; ++jj) {
           const float f = ph[j][jj], fn = pn[j][jj];
           const float a1n = n1n[j][jj] - fn, a0n = n0n[j][jj] - fn;
           const float ds = (fn - f) * (fn + f);
@@ -379,15 +424,15 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
         }
     }
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
+    for (int jj = 0; jj < JJ; ++jj) {
       r0[jj] = row16_sum(r0[jj]);
       r1[jj] = row16_sum(r1[jj]);
     }
     if (p == 0) {
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        red0[wv * 16 + 4 * g + jj] = r0[jj];
-        red1[wv * 16 + 4 * g + jj] = r1[jj];
+      for (int jj = 0; jj < JJ; ++jj) {
+        red0[cw * 16 + 4 * g + jb + jj] = r0[jj];
+        red1[cw * 16 + 4 * g + jb + jj] = r1[jj];
       }
     }
     __syncthreads();
@@ -419,16 +464,16 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
 #pragma unroll
       for (int j = 0; j < NBW; ++j)
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          const int ti = base + 4 * g + jj;
+        for (int jj = 0; jj < JJ; ++jj) {
+          const int ti = base + 4 * g + jb + jj;
           if (oval[jj] && cval[j]) a.prop[(size_t)ti * d + col[j]] = pn[j][jj];
         }
     }
 #pragma unroll
     for (int j = 0; j < NBW; ++j)
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj)
-        if ((mask >> (4 * g + jj)) & 1ull) ph[j][jj] = pn[j][jj];
+      for (int jj = 0; jj < JJ; ++jj)
+        if ((mask >> (4 * g + jb + jj)) & 1ull) ph[j][jj] = pn[j][jj];
     nacc += __popcll(mask);
   }
 
@@ -436,15 +481,17 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
 #pragma unroll
   for (int j = 0; j < NBW; ++j)
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) xo[(4 * g + jj) * XS + col[j]] = ph[j][jj];
+    for (int jj = 0; jj < JJ; ++jj) xo[(4 * g + jb + jj) * XS + col[j]] = ph[j][jj];
   __syncthreads();
-  float r0[4] = {0.f, 0.f, 0.f, 0.f}, r1[4] = {0.f, 0.f, 0.f, 0.f};
+  float r0[JJ], r1[JJ];
+#pragma unroll
+  for (int jj = 0; jj < JJ; ++jj) r0[jj] = r1[jj] = 0.f;
 #pragma unroll
   for (int j = 0; j < NBW; ++j) {
     if (!cval[j]) continue;
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
-      const int rb = (4 * g + jj) * XS;
+    for (int jj = 0; jj < JJ; ++jj) {
+      const int rb = (4 * g + jb + jj) * XS;
       const float f = ph[j][jj];
       const float a1 = xo[rb + y1[j]] - f, a0 = xo[rb + y0[j]] - f;
       const float f2 = f * f;
@@ -453,22 +500,22 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
     }
   }
 #pragma unroll
-  for (int jj = 0; jj < 4; ++jj) {
+  for (int jj = 0; jj < JJ; ++jj) {
     r0[jj] = row16_sum(r0[jj]);
     r1[jj] = row16_sum(r1[jj]);
   }
   if (p == 0) {
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
-      red0[wv * 16 + 4 * g + jj] = r0[jj];
-      red1[wv * 16 + 4 * g + jj] = r1[jj];
+    for (int jj = 0; jj < JJ; ++jj) {
+      red0[cw * 16 + 4 * g + jb + jj] = r0[jj];
+      red1[cw * 16 + 4 * g + jb + jj] = r1[jj];
     }
   }
   // field write-back
 #pragma unroll
   for (int j = 0; j < NBW; ++j)
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj)
+    for (int jj = 0; jj < JJ; ++jj)
       if (oval[jj] && cval[j]) a.dst[(size_t)orow[jj] * d + col[j]] = ph[j][jj];
   __syncthreads();
   if (wv == 0 && lane < 16) {
@@ -491,19 +538,19 @@ __global__ __launch_bounds__(64 * C::W) void mutate_kernel(MutateArgs a) {
   }
 }
 
-template <int DP, int W, int KIND>
+template <int DP, int W, int KIND, int H>
 int launch_kind(const MutateArgs& a, int precision, hipStream_t s) {
   const unsigned grid = (unsigned)((a.n + 15) / 16);
-  const dim3 block(64 * W);
+  const dim3 block(64 * W * H);
   switch (precision) {
     case PHI4_FP32:
-      mutate_kernel<Cfg<DP, W, PHI4_FP32, KIND>><<<grid, block, 0, s>>>(a);
+      mutate_kernel<Cfg<DP, W, PHI4_FP32, KIND, H>><<<grid, block, 0, s>>>(a);
       break;
     case PHI4_BF16:
-      mutate_kernel<Cfg<DP, W, PHI4_BF16, KIND>><<<grid, block, 0, s>>>(a);
+      mutate_kernel<Cfg<DP, W, PHI4_BF16, KIND, H>><<<grid, block, 0, s>>>(a);
       break;
     case PHI4_FP16:
-      mutate_kernel<Cfg<DP, W, PHI4_FP16, KIND>><<<grid, block, 0, s>>>(a);
+      mutate_kernel<Cfg<DP, W, PHI4_FP16, KIND, H>><<<grid, block, 0, s>>>(a);
       break;
     default:
       return PHI4_EINVAL;
@@ -511,9 +558,10 @@ int launch_kind(const MutateArgs& a, int precision, hipStream_t s) {
   return PHI4_OK;
 }
 
-template <int DP, int W>
+template <int DP, int W, int H = 2>
 int launch_dp(const MutateArgs& a, int precision, hipStream_t s) {
-  return a.kind == 1 ? launch_kind<DP, W, 1>(a, precision, s) : launch_kind<DP, W, 0>(a, precision, s);
+  return a.kind == 1 ? launch_kind<DP, W, 1, H>(a, precision, s)
+                     : launch_kind<DP, W, 0, H>(a, precision, s);
 }
 
 }  // namespace
@@ -534,7 +582,7 @@ int launch_mutate(const MutateArgs& a, int precision, hipStream_t s) {
   if (dp <= 32) return launch_dp<32, 2>(a, precision, s);
   if (dp <= 64) return launch_dp<64, 4>(a, precision, s);
   if (dp <= 128) return launch_dp<128, 4>(a, precision, s);
-  return launch_dp<256, 8>(a, precision, s);
+  return launch_dp<256, 8, 1>(a, precision, s);   // 1024 threads would cap a wave at 128 VGPRs
 }
 
 }  // namespace phi4
