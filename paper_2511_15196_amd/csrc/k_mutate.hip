@@ -17,7 +17,7 @@
 // registers for the whole sweep and forms the set's whole product, whose
 // MFMA output layout gives lane (p, g) rows 4g..4g+3 of column 16 nb + p;
 // of these the wave owns 4 / H rows, whose fields it holds and whose
-// stencil and Metropolis terms it evaluates.  With H = 2 at d <= 128 a tile
+// stencil and Metropolis terms it evaluates.  With H = 2 at d <= 64 a tile
 // of 16 particles runs 8 waves instead of 4, so that at N = 4096 every SIMD
 // holds two waves to hide each other's latency (the per-site sums and every
 // result are unchanged, bit for bit).  dS is accumulated from per-site
@@ -581,7 +581,9 @@ int launch_mutate(const MutateArgs& a, int precision, hipStream_t s) {
   if (dp <= 16) return launch_dp<16, 1>(a, precision, s);
   if (dp <= 32) return launch_dp<32, 2>(a, precision, s);
   if (dp <= 64) return launch_dp<64, 4>(a, precision, s);
-  if (dp <= 128) return launch_dp<128, 4>(a, precision, s);
+  // d > 64: each wave forms two or more column blocks' float32 products, and
+  // splitting the rows would repeat that MFMA work in both waves of a set
+  if (dp <= 128) return launch_dp<128, 4, 1>(a, precision, s);
   return launch_dp<256, 8, 1>(a, precision, s);   // 1024 threads would cap a wave at 128 VGPRs
 }
 
