@@ -41,7 +41,7 @@ VALU_PEAK = 256 * 4 * 16 * 2.4e9
 # 256 MiB device-to-device copy read and write 256 MiB on the same counters),
 # valid only for the kernel sources they were taken on.
 TRAFFIC = dict(bytes_per_launch=(522.67 * 1.99980 + 1072.0) * 1024,
-               sources={"k_mutate.hip": "328744d734fe6b2d9b6d12e4b572f2440d5ba986f2720580c66ea7079d9854d8",
+               sources={"k_mutate.hip": "6488e5e7d613b4e490481ffbfa8fd214f121e77d4fbb429d377f5ba4295a860a",
                         "common.hpp": "4097ce027518c90000269a1063c71e114baf0749c9547a9753dffa4777d92be5"})
 
 

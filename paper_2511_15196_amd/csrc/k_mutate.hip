@@ -17,10 +17,10 @@
 // registers for the whole sweep and forms the set's whole product, whose
 // MFMA output layout gives lane (p, g) rows 4g..4g+3 of column 16 nb + p;
 // of these the wave owns 4 / H rows, whose fields it holds and whose
-// stencil and Metropolis terms it evaluates.  With H = 2 at d <= 64 a tile
-// of 16 particles runs 8 waves instead of 4, so that at N = 4096 every SIMD
-// holds two waves to hide each other's latency (the per-site sums and every
-// result are unchanged, bit for bit).  dS is accumulated from per-site
+// stencil and Metropolis terms it evaluates.  H = 2 at d <= 64 doubles the
+// waves of a tile (8 instead of 4 at d = 64), so that at N = 4096 every
+// SIMD holds two waves to hide each other's latency (the per-site sums and
+// every result are unchanged, bit for bit).  dS is accumulated from per-site
 // differences so that float32 does not cancel |S|.
 //
 // Pipelining: the normals do not depend on the fields, so the tile's
