@@ -562,7 +562,7 @@ __global__ __launch_bounds__(kAT) void accept_kernel(AcceptArgs a) {
   }
 }
 
-// The same accept for d <= 256: one wave per particle, four particles per
+// The same accept for d <= 512: one wave per particle, four particles per
 // workgroup (a 256-thread workgroup per particle leaves most lanes idle at
 // these sizes).  Every lane of a wave forms the same sums (DPP reduction)
 // and takes the same decision; lane 0 writes the per-particle outputs.
@@ -749,21 +749,21 @@ void launch_gemm(int tile, const LargeScratch& w, const float* cur, const int32_
 template <bool CONSTRAINED, bool IND = false>
 void launch_accept(int per, int n, size_t lds, const AcceptArgs& aa, hipStream_t st) {
   static_assert(PHI4_MAX_SITES <= 16 * kAT, "accept stages at most 16 sites per thread");
-  if (aa.d <= 256) {   // one wave per particle
+  if (aa.d <= 512) {   // one wave per particle
     const unsigned g = (unsigned)((n + kAW - 1) / kAW);
     const size_t wl = kAW * 2 * (size_t)aa.d * sizeof(float);
     if (aa.d <= 64)
       accept_wave_kernel<CONSTRAINED, 1, IND><<<g, 64 * kAW, wl, st>>>(aa);
     else if (aa.d <= 128)
       accept_wave_kernel<CONSTRAINED, 2, IND><<<g, 64 * kAW, wl, st>>>(aa);
-    else
+    else if (aa.d <= 256)
       accept_wave_kernel<CONSTRAINED, 4, IND><<<g, 64 * kAW, wl, st>>>(aa);
+    else
+      accept_wave_kernel<CONSTRAINED, 8, IND><<<g, 64 * kAW, wl, st>>>(aa);
     return;
   }
   const bool vec = aa.d % 4 == 0;   // rows 16-byte aligned: quad loads
-  if (per <= 2)
-    accept_kernel<CONSTRAINED, 2, IND><<<n, kAT, lds, st>>>(aa);
-  else if (per <= 4)
+  if (per <= 4)   // d > 512 here, so per >= 3
     vec ? accept_kernel<CONSTRAINED, 4, IND, true><<<n, kAT, lds, st>>>(aa)
         : accept_kernel<CONSTRAINED, 4, IND><<<n, kAT, lds, st>>>(aa);
   else if (per <= 8)
