@@ -168,7 +168,7 @@ def oracle_tempered(phi, prop, beta, L, seed, run, level, step, rows, m2=-4.0, l
 
 @pytest.mark.parametrize("L,n,beta", [(4, 256, 0.0), (8, 4096, 0.3), (8, 1000, 1.0),
                                       (10, 333, 0.7), (16, 2000, 0.5), (17, 300, 0.5),
-                                      (18, 300, 0.5), (32, 200, 0.5)])
+                                      (18, 300, 0.5), (22, 203, 0.5), (32, 200, 0.5)])
 def test_tempered_decisions(L, n, beta):
     say("tempered", L, n, beta)
     phi = synth.broken_phase_fields(n, n, L)
@@ -190,7 +190,7 @@ def test_tempered_decisions(L, n, beta):
     assert r["acc"] == int(r["flags"].sum())
 
 
-@pytest.mark.parametrize("L,n", [(8, 3000), (17, 400), (32, 150)])
+@pytest.mark.parametrize("L,n", [(8, 3000), (17, 400), (22, 150), (32, 150)])
 def test_constrained_decisions(L, n):
     pv = 4.0
     phi = synth.broken_phase_fields(77, n, L, v=0.2, noise=0.5)
