@@ -40,9 +40,9 @@ VALU_PEAK = 256 * 4 * 16 * 2.4e9
 # counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0: the factors that make a
 # 256 MiB device-to-device copy read and write 256 MiB on the same counters),
 # valid only for the kernel sources they were taken on.
-TRAFFIC = dict(bytes_per_launch=(522.67 * 1.99980 + 1072.0) * 1024,
-               sources={"k_mutate.hip": "6488e5e7d613b4e490481ffbfa8fd214f121e77d4fbb429d377f5ba4295a860a",
-                        "common.hpp": "4097ce027518c90000269a1063c71e114baf0749c9547a9753dffa4777d92be5"})
+TRAFFIC = dict(bytes_per_launch=(522.71 * 1.99980 + 1072.0) * 1024,
+               sources={"k_mutate.hip": "dc7ad60baebd00fc99def8042166cfc5d8093c1b793440617573e725636d07a0",
+                        "common.hpp": "20b4425db3d352bda5372818ee91d001ee78f716f53557a5c19283103346c47b"})
 
 
 def traffic_per_launch():

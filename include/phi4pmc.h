@@ -274,8 +274,10 @@ int phi4_set_tile(int32_t n, int32_t d, int32_t precision, int32_t rows, int32_t
                   int32_t threads);
 
 /* Kernel timing: while enabled, every mutation launch of
- * smc_mutate / smc_run / ns_step is bracketed by HIP events on the handle's
- * stream (the no-op launch smc_run enqueues after the final sweep is not
+ * smc_mutate / smc_run / ns_step is timed by a pair of HIP events on the
+ * handle's stream: the fused random-walk sweep (d <= 256) records them on its
+ * own dispatch packet, every other mutation launch is bracketed by two event
+ * records (the no-op launch smc_run enqueues after the final sweep is not
  * counted). */
 int phi4_set_timing(void* handle, int32_t enabled);
 

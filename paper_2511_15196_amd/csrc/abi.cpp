@@ -212,10 +212,14 @@ struct Handle {
   size_t tused;                                        // pairs recorded
 };
 
-// Brackets one mutation launch with a pair of timing events.
+// Times one mutation launch with a pair of events: the fused sweep records
+// them on its own dispatch packet (attach), any other launch is bracketed by
+// two event records on the stream (begin and the destructor).
 struct TimedLaunch {
   Handle* h;
-  hipEvent_t stop = nullptr;
+  hipEvent_t start = nullptr, stop = nullptr;
+  bool attached = false;
+  bool launched = true;   // attached pairs count only if the launch happened
   explicit TimedLaunch(Handle* hh) : h(hh) {
     if (!h->timing) return;
     if (h->tused == h->tev.size()) {
@@ -226,13 +230,27 @@ struct TimedLaunch {
       }
       h->tev.push_back(p);
     }
-    (void)hipEventRecord(h->tev[h->tused].first, h->stream);
+    start = h->tev[h->tused].first;
     stop = h->tev[h->tused].second;
+  }
+  // the fused sweep launches exactly when these hold (launch_mutate)
+  void attach(MutateArgs& m) {
+    if (!start || m.n <= 0 || m.n_steps < 0 || m.d > kFusedMaxSites || m.passes) return;
+    m.ev_start = start;
+    m.ev_stop = stop;
+    attached = true;
+  }
+  void begin() {
+    if (start && !attached) (void)hipEventRecord(start, h->stream);
   }
   ~TimedLaunch() {
     if (!stop) return;
-    (void)hipEventRecord(stop, h->stream);
-    ++h->tused;
+    if (!attached) {
+      (void)hipEventRecord(stop, h->stream);
+      ++h->tused;
+    } else if (launched) {
+      ++h->tused;
+    }
   }
 };
 
@@ -350,6 +368,8 @@ int enqueue_mutate(Handle* h) {
   int rc = PHI4_OK;
   {
     TimedLaunch tl(h);
+    if (h->smc.kernel == PHI4_KERNEL_RW) tl.attach(m);
+    tl.begin();
     if (h->smc.kernel == PHI4_KERNEL_IRMH) {
       rc = launch_irmh_sweep(m, b.A, b.irmh, h->stream);
     } else if (h->smc.kernel == PHI4_KERNEL_HMC) {
@@ -378,6 +398,7 @@ int enqueue_mutate(Handle* h) {
       launch_hmc_sweep(ha, h->stream);
     } else {
       rc = launch_mutate(m, h->precision, h->stream);
+      tl.launched = rc == PHI4_OK;
     }
   }
   if (rc) return fail(rc, "smc_mutate: unsupported shape");
@@ -945,8 +966,11 @@ int ns_step(void* handle, int32_t* done_host) {
   int rc;
   {
     TimedLaunch tl(h);
+    if (h->ns.kernel != PHI4_NS_SLICE) tl.attach(m);
+    tl.begin();
     rc = h->ns.kernel == PHI4_NS_SLICE ? launch_slice_sweep(m, h->szero, h->stream)
                                        : launch_mutate(m, h->precision, h->stream);
+    tl.launched = rc == PHI4_OK;
   }
   if (rc) return fail(rc, "ns_step: unsupported shape");
   rc = hip_check("ns_step");

@@ -287,6 +287,8 @@ struct MutateArgs {
   float* prop;             // test output (optional), indexed by tile slot
   LargeScratch large;      // scratch of the three-pass sweep
   int32_t passes;          // 1: three passes per step even for d <= kFusedMaxSites
+  hipEvent_t ev_start;     // if set: timing events recorded by the fused sweep's own
+  hipEvent_t ev_stop;      // dispatch (no separate event packets on the stream)
 };
 
 // k_mutate.hip (fused sweep, d <= kFusedMaxSites; larger d goes to k_large.hip)

@@ -35,6 +35,8 @@
 // negating z flips s, so the increment is odd in z bit for bit at the cost
 // of one product; with the symmetric normals the proposal law is exactly
 // symmetric, so the Metropolis ratio needs no Hastings term.
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 #include "common.hpp"
@@ -538,19 +540,27 @@ __global__ __launch_bounds__(C::NT) void mutate_kernel(MutateArgs a) {
   }
 }
 
+// One launch; with timing events they ride on the dispatch packet itself.
+template <class C>
+void launch_cfg(const MutateArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)((a.n + 15) / 16)), block(C::NT);
+  if (a.ev_start)
+    hipExtLaunchKernelGGL(mutate_kernel<C>, grid, block, 0, s, a.ev_start, a.ev_stop, 0, a);
+  else
+    mutate_kernel<C><<<grid, block, 0, s>>>(a);
+}
+
 template <int DP, int W, int KIND, int H>
 int launch_kind(const MutateArgs& a, int precision, hipStream_t s) {
-  const unsigned grid = (unsigned)((a.n + 15) / 16);
-  const dim3 block(64 * W * H);
   switch (precision) {
     case PHI4_FP32:
-      mutate_kernel<Cfg<DP, W, PHI4_FP32, KIND, H>><<<grid, block, 0, s>>>(a);
+      launch_cfg<Cfg<DP, W, PHI4_FP32, KIND, H>>(a, s);
       break;
     case PHI4_BF16:
-      mutate_kernel<Cfg<DP, W, PHI4_BF16, KIND, H>><<<grid, block, 0, s>>>(a);
+      launch_cfg<Cfg<DP, W, PHI4_BF16, KIND, H>>(a, s);
       break;
     case PHI4_FP16:
-      mutate_kernel<Cfg<DP, W, PHI4_FP16, KIND, H>><<<grid, block, 0, s>>>(a);
+      launch_cfg<Cfg<DP, W, PHI4_FP16, KIND, H>>(a, s);
       break;
     default:
       return PHI4_EINVAL;
